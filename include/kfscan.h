@@ -1,0 +1,142 @@
+/*
+ * kfscan.h -- C ABI of the MI355X (gfx950) parallel-in-time Kalman filter and
+ * smoothers of Sarkka & Garcia-Fernandez, "On the performance of prefix-sum
+ * parallel Kalman filters and smoothers on GPUs" (arXiv 2511.10363).
+ *
+ * Every entry point computes an all-prefix-sum (scan) over the paper's
+ * associative elements on the GPU:
+ *   kf_filter            Algorithm 5: filtering elements (A, b, C, eta, J) of
+ *                        eqs. pkf_init1..pkf_init3, scanned with the operator
+ *                        of Lemma 1; x_{k|k} = b_k^+, P_{k|k} = C_k^+.
+ *   kf_smooth_rts        Algorithm 6: the filter pass, then smoothing elements
+ *                        (E, g, L) of eqs. prts_init1/prts_init2 reverse-scanned
+ *                        with the operator of Lemma 2; x_{k|T} = g_k^+, P_{k|T} = L_k^+.
+ *   kf_smooth_twofilter  Algorithm 7: the filter pass, a reverse scan of
+ *                        (a_2, ..., a_T, e) with the operator of Lemma 1 giving
+ *                        eta_{k|k+1:T}, J_{k|k+1:T}, and the two-filter
+ *                        combination (eqs. mean_tf_combination, cov_tf_combination).
+ *
+ * Model (Sec. III-A, eqs. transition_density_Kalman, measurement_density_Kalman,
+ * with u = d = 0 and a time-invariant model):
+ *   x_k = F x_{k-1} + q,  q ~ N(0, Q);   y_k = H x_k + r,  r ~ N(0, R);
+ *   prior x_0 ~ N(m0, P0), i.e. m0 = x_{0|0}, P0 = P_{0|0}.  Step k = 1..T first
+ *   predicts from x_{k-1|k-1}, then updates with y_k; results for step k are
+ *   stored at row k-1.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller; the
+ * library never allocates, frees or retains it.  Storage dtype of every array
+ * is float64 for KF_PREC_F64 and float32 for the two other precisions.
+ * Layouts are dense row-major:
+ *   F, Q, P0 : [nx][nx]      H : [ny][nx]      R : [ny][ny]      m0 : [nx]
+ *   y        : [nseq][T][ny]                   (sequences back to back)
+ *   m_filt, m_smooth : [nseq][T][nx]
+ *   P_filt, P_smooth : [nseq][T][nx][nx]      (exactly symmetric on output)
+ * Q, R, P0 must be symmetric positive semi-definite with H Q H^T + R and the
+ * predicted covariances positive definite (the smoothers factorise
+ * F P_{k|k} F^T + Q).  The library does not inspect values: a numerical
+ * breakdown produces non-finite outputs, never an error code.
+ *
+ * Workspace: device memory of at least kf_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller, with no initialisation required: the first
+ * kernel of every call zeroes the workspace's control words (tile tickets,
+ * look-back status words), so one workspace serves any sequence of calls
+ * issued in order on one stream, whatever their shapes and precisions.
+ * Calls that may run concurrently need distinct workspaces.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Calls are asynchronous: they validate arguments on the host,
+ * enqueue kernels and return; the caller synchronises.  No host memory is
+ * read or written after return.
+ *
+ * Errors: argument checks happen on the host before anything is enqueued;
+ * on any error nothing is launched and the outputs are untouched.
+ */
+#ifndef KFSCAN_H
+#define KFSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KFSCAN_ABI_VERSION 1
+
+typedef enum kf_status {
+    KF_OK = 0,
+    KF_ERR_INVALID_ARG = 1,  /* null pointer, bad size, unknown enum value       */
+    KF_ERR_UNSUPPORTED = 2,  /* (nx, ny) or precision/scan combination not built */
+    KF_ERR_WORKSPACE = 3,    /* workspace too small or misaligned                */
+    KF_ERR_DEVICE = 4        /* the HIP runtime rejected a launch                */
+} kf_status;
+
+typedef enum kf_precision {
+    KF_PREC_F64 = 0,          /* FP64 storage and arithmetic                        */
+    KF_PREC_F32 = 1,          /* FP32 storage and arithmetic                        */
+    KF_PREC_F32_F64SOLVE = 2  /* FP32 storage and scans; the (I + C_i J_j) and
+                                 (I + P J) factorisations and solves, and the
+                                 assembly of symmetric covariance blocks, in FP64   */
+} kf_precision;
+
+typedef enum kf_scan {
+    KF_SCAN_AUTO = 0,          /* library default (single-pass look-back)          */
+    KF_SCAN_LOOKBACK = 1,      /* single-pass tiled scan with decoupled look-back  */
+    KF_SCAN_BLELLOCH = 2,      /* Algorithm 2, one kernel per tree level           */
+    KF_SCAN_HILLIS_STEELE = 3  /* Algorithm 1, one kernel per doubling level       */
+} kf_scan;
+
+typedef struct kf_problem {
+    int32_t nx;            /* state dimension n   (see kf_supported)              */
+    int32_t ny;            /* measurement dimension m                             */
+    int32_t precision;     /* kf_precision                                        */
+    int32_t scan;          /* kf_scan                                             */
+    int64_t T;             /* steps per sequence, >= 1                            */
+    int64_t nseq;          /* number of sequences sharing the model, >= 1         */
+    const void *F, *Q, *H, *R, *m0, *P0;  /* model, device                         */
+    const void *y;                         /* measurements, device                  */
+    void *m_filt, *P_filt;                 /* filter outputs, device                */
+    void *m_smooth, *P_smooth;             /* smoother outputs, device (smoothers)  */
+} kf_problem;
+
+/* ABI version (KFSCAN_ABI_VERSION). */
+int kf_abi_version(void);
+
+/* Static description of a status code (never NULL). */
+const char *kf_status_string(kf_status s);
+
+/* 1 if kernels for (nx, ny, precision) are compiled in, else 0. */
+int kf_supported(int32_t nx, int32_t ny, int32_t precision);
+
+/* Bytes of workspace that kf_filter / kf_smooth_rts / kf_smooth_twofilter need
+ * for this problem (the largest of the three, so one workspace serves all).
+ * Only the size fields, precision and scan of *p are read. */
+kf_status kf_workspace_size(const kf_problem *p, size_t *bytes);
+
+/* Zero-fill `bytes` of device memory on `stream` with a fill kernel (a
+ * convenience; workspaces need no clearing). */
+kf_status kf_workspace_clear(void *workspace, size_t bytes, void *stream);
+
+/* Diagnostic, synchronises `stream`: sets *timed_out to 1 if a look-back wait
+ * in the last call that used this workspace gave up (a predecessor tile
+ * never published within about a second, so that call's outputs are
+ * invalid), else 0.  *p must describe that call. */
+kf_status kf_workspace_timed_out(const kf_problem *p, const void *workspace,
+                                 size_t workspace_bytes, int32_t *timed_out, void *stream);
+
+/* Algorithm 5: writes m_filt, P_filt. */
+kf_status kf_filter(const kf_problem *p, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Algorithm 6: writes m_filt, P_filt (the filter pass) and m_smooth, P_smooth. */
+kf_status kf_smooth_rts(const kf_problem *p, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* Algorithm 7: writes m_filt, P_filt (the forward pass) and m_smooth, P_smooth. */
+kf_status kf_smooth_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KFSCAN_H */

@@ -1,0 +1,73 @@
+// kf_inst.hpp -- kernel launches for one (N, M, precision); included by the
+// per-precision translation units, which list the shapes that are built.
+#pragma once
+#include "kf_kernels.hpp"
+#include "kf_plan.hpp"
+
+namespace kfs {
+
+template <int N, int M, class P>
+kf_status run_shape(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
+  using R = typename P::R;
+  constexpr int B = kBlock;
+  constexpr int IT = items_per_thread(N);
+  R* cst = reinterpret_cast<R*>(ws + L.cst);
+  const size_t prep_blocks = (L.ctrl_words + 255) / 256;
+  hipLaunchKernelGGL((k_prepare<N, M, R>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
+                     dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                     static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                     static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
+                     reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+  const unsigned grid = (unsigned)(L.ntiles * p.nseq);
+  auto args = [&](int slot) {
+    ScanArgs<R> a{};
+    a.cst = cst;
+    a.y = static_cast<const R*>(p.y);
+    a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
+    a.agg = reinterpret_cast<R*>(ws + L.agg[slot]);
+    a.pre = reinterpret_cast<R*>(ws + L.pre[slot]);
+    a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
+    a.T = p.T;
+    a.ntiles = L.ntiles;
+    a.nseq = p.nseq;
+    return a;
+  };
+  ScanArgs<R> fa = args(0);
+  fa.m_out = static_cast<R*>(p.m_filt);
+  fa.P_out = static_cast<R*>(p.P_filt);
+  hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, fa);
+  if (op != OP_FILTER) {
+    ScanArgs<R> ba = args(1);
+    ba.m_in = static_cast<const R*>(p.m_filt);
+    ba.P_in = static_cast<const R*>(p.P_filt);
+    ba.m_out = static_cast<R*>(p.m_smooth);
+    ba.P_out = static_cast<R*>(p.P_smooth);
+    if (op == OP_RTS)
+      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, ba);
+    else
+      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, ba);
+  }
+  return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+}
+
+// Shapes compiled into the library.
+#define KFS_SHAPES(X) \
+  X(1, 1)             \
+  X(2, 1)             \
+  X(2, 2)             \
+  X(3, 1)             \
+  X(3, 2)             \
+  X(4, 1)             \
+  X(4, 2)             \
+  X(4, 4)
+
+template <class P>
+kf_status run_prec(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
+#define KFS_CASE(n, m) \
+  if (p.nx == n && p.ny == m) return run_shape<n, m, P>(op, p, ws, L, st);
+  KFS_SHAPES(KFS_CASE)
+#undef KFS_CASE
+  return KF_ERR_UNSUPPORTED;
+}
+
+}  // namespace kfs

@@ -1,0 +1,8 @@
+// Kernel instantiations for precision policy PrecMixed.
+#include "kf_inst.hpp"
+
+namespace kfs {
+kf_status run_mixed(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
+  return run_prec<PrecMixed>(op, p, ws, L, st);
+}
+}  // namespace kfs

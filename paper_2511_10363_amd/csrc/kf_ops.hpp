@@ -1,0 +1,353 @@
+// kf_ops.hpp -- the paper's associative elements and operators on gfx950.
+//
+// Filtering element a = (A, b, C, eta, J)  (Sec. IV-C, eqs. pkf_init1..3)
+// Filtering operator                        (Lemma 1)
+// Smoothing element a = (E, g, L)           (Sec. IV-D, eqs. prts_init1..2)
+// Smoothing operator                        (Lemma 2)
+//
+// Precision policy P: P::R is the element/storage type, P::S the type of the
+// (I + C_i J_j) factorisation, its solves and the assembly of symmetric
+// covariance blocks.  For KF_PREC_F32_F64SOLVE, R = float and S = double.
+#pragma once
+#include "kf_math.hpp"
+
+namespace kfs {
+
+template <class R_, class S_> struct Prec {
+  using R = R_;
+  using S = S_;
+};
+using PrecF64 = Prec<double, double>;
+using PrecF32 = Prec<float, float>;
+using PrecMixed = Prec<float, double>;
+
+template <int N, class R> struct FElem {
+  R A[N][N];
+  R b[N];
+  R C[N][N];
+  R e[N];  // eta
+  R J[N][N];
+  static constexpr int SIZE = 3 * N * N + 2 * N;
+};
+
+template <int N, class R> struct SElem {
+  R E[N][N];
+  R g[N];
+  R L[N][N];
+  static constexpr int SIZE = 2 * N * N + N;
+};
+
+// Visit every scalar of an element in its flat (storage) order.
+template <int N, class R, class F> KF_DEV void each(FElem<N, R>& x, F f) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.A[i][j], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i) f(x.b[i], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.C[i][j], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i) f(x.e[i], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.J[i][j], k++);
+}
+
+template <int N, class R, class F> KF_DEV void each(SElem<N, R>& x, F f) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.E[i][j], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i) f(x.g[i], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.L[i][j], k++);
+}
+
+// Two-sided identities (I, 0, 0, 0, 0) and (I, 0, 0).
+template <int N, class R> KF_DEV void set_identity(FElem<N, R>& x) {
+  each(x, [](R& v, int) { v = R(0); });
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.A[i][i] = R(1);
+}
+template <int N, class R> KF_DEV void set_identity(SElem<N, R>& x) {
+  each(x, [](R& v, int) { v = R(0); });
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.E[i][i] = R(1);
+}
+
+// ---------------------------------------------------------------------------
+// Lemma 1.  With M = I + C_i J_j, the transposed factor (I + J_j C_i)^{-1}
+// equals M^{-T}, so A_i^T (I + J_j C_i)^{-1} = Z^T with Z = M^{-1} A_i and
+// one factorisation with 2N+1 right-hand sides serves all five outputs:
+//   A_ij = A_j Z                       b_ij = A_j M^{-1}(b_i + C_i eta_j) + b_j
+//   C_ij = A_j (M^{-1} C_i) A_j^T + C_j  eta_ij = Z^T (eta_j - J_j b_i) + eta_i
+//   J_ij = Z^T (J_j A_i) + J_i
+// ---------------------------------------------------------------------------
+template <int N, class P>
+KF_DEV FElem<N, typename P::R> fcombine(const FElem<N, typename P::R>& x,
+                                        const FElem<N, typename P::R>& y) {
+  using R = typename P::R;
+  using S = typename P::S;
+  S M[N][N];
+  mm<N, N, N, S>(x.C, y.J, M);
+#pragma unroll
+  for (int i = 0; i < N; ++i) M[i][i] += S(1);
+  int piv[N];
+  S dinv[N];
+  lu_factor<N, S>(M, piv, dinv);
+  S B[N][2 * N + 1];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      B[r][c] = S(x.A[r][c]);
+      B[r][N + c] = S(x.C[r][c]);
+    }
+    S s = S(x.b[r]);
+#pragma unroll
+    for (int t = 0; t < N; ++t) s += S(x.C[r][t]) * S(y.e[t]);
+    B[r][2 * N] = s;
+  }
+  lu_solve<N, 2 * N + 1, S>(M, piv, dinv, B);
+  R Z[N][N], Y[N][N], v[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      Z[r][c] = R(B[r][c]);
+      Y[r][c] = R(B[r][N + c]);
+    }
+    v[r] = R(B[r][2 * N]);
+  }
+  FElem<N, R> o;
+  mm<N, N, N, R>(y.A, Z, o.A);
+  R Av[N];
+  mv<N, N, R>(y.A, v, Av);
+#pragma unroll
+  for (int i = 0; i < N; ++i) o.b[i] = Av[i] + y.b[i];
+  R AY[N][N];
+  mm<N, N, N, R>(y.A, Y, AY);
+  sym_xyt_plus<N, N, S>(AY, y.A, y.C, o.C);
+  R Jb[N], w[N], Ztw[N];
+  mv<N, N, R>(y.J, x.b, Jb);
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = y.e[i] - Jb[i];
+  mtv<N, N, R>(Z, w, Ztw);
+#pragma unroll
+  for (int i = 0; i < N; ++i) o.e[i] = Ztw[i] + x.e[i];
+  R JA[N][N];
+  mm<N, N, N, R>(y.J, x.A, JA);
+  sym_xty_plus<N, N, S>(Z, JA, x.J, o.J);
+  return o;
+}
+
+// Lemma 1 with a left operand whose A is zero (any prefix that starts at
+// step 1, since A_1 = 0): only b and C of the result are formed,
+//   b' = A_j M^{-1}(x + P eta_j) + b_j,   C' = A_j M^{-1} P A_j^T + C_j,
+// M = I + P J_j.  (x, P) is the filtering mean/covariance so far.
+template <int N, class P>
+KF_DEV void fapply(typename P::R (&x)[N], typename P::R (&Pm)[N][N],
+                   const FElem<N, typename P::R>& y) {
+  using R = typename P::R;
+  using S = typename P::S;
+  S M[N][N];
+  mm<N, N, N, S>(Pm, y.J, M);
+#pragma unroll
+  for (int i = 0; i < N; ++i) M[i][i] += S(1);
+  int piv[N];
+  S dinv[N];
+  lu_factor<N, S>(M, piv, dinv);
+  S B[N][N + 1];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    S s = S(x[r]);
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      B[r][c] = S(Pm[r][c]);
+      s += S(Pm[r][c]) * S(y.e[c]);
+    }
+    B[r][N] = s;
+  }
+  lu_solve<N, N + 1, S>(M, piv, dinv, B);
+  R Y[N][N], v[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) Y[r][c] = R(B[r][c]);
+    v[r] = R(B[r][N]);
+  }
+  R Av[N];
+  mv<N, N, R>(y.A, v, Av);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = Av[i] + y.b[i];
+  R AY[N][N];
+  mm<N, N, N, R>(y.A, Y, AY);
+  sym_xyt_plus<N, N, S>(AY, y.A, y.C, Pm);
+}
+
+// Lemma 1 with a right operand that is a suffix of the backward pass, of
+// which only (eta_j, J_j) is needed: returns the (eta, J) part of a_i (x) s,
+//   eta' = Z^T (eta_j - J_j b_i) + eta_i,   J' = Z^T (J_j A_i) + J_i,
+// Z = (I + C_i J_j)^{-1} A_i.  This is the backward information-filter step
+// (eqs. tf_vector_pred..tf_matrix_upd) written in element form.
+template <int N, class P>
+KF_DEV void fapply_back(const FElem<N, typename P::R>& a, typename P::R (&eta)[N],
+                        typename P::R (&J)[N][N]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  S M[N][N];
+  mm<N, N, N, S>(a.C, J, M);
+#pragma unroll
+  for (int i = 0; i < N; ++i) M[i][i] += S(1);
+  int piv[N];
+  S dinv[N];
+  lu_factor<N, S>(M, piv, dinv);
+  S B[N][N];
+  copy_mat<N, N, S>(a.A, B);
+  lu_solve<N, N, S>(M, piv, dinv, B);
+  R Z[N][N];
+  copy_mat<N, N, R>(B, Z);
+  R Jb[N], w[N], Ztw[N];
+  mv<N, N, R>(J, a.b, Jb);
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = eta[i] - Jb[i];
+  mtv<N, N, R>(Z, w, Ztw);
+  R JA[N][N];
+  mm<N, N, N, R>(J, a.A, JA);
+#pragma unroll
+  for (int i = 0; i < N; ++i) eta[i] = Ztw[i] + a.e[i];
+  sym_xty_plus<N, N, S>(Z, JA, a.J, J);
+}
+
+// ---------------------------------------------------------------------------
+// Lemma 2: E_ij = E_i E_j, g_ij = E_i g_j + g_i, L_ij = E_i L_j E_i^T + L_i.
+// ---------------------------------------------------------------------------
+template <int N, class P>
+KF_DEV SElem<N, typename P::R> scombine(const SElem<N, typename P::R>& x,
+                                        const SElem<N, typename P::R>& y) {
+  using R = typename P::R;
+  using S = typename P::S;
+  SElem<N, R> o;
+  mm<N, N, N, R>(x.E, y.E, o.E);
+  R Eg[N];
+  mv<N, N, R>(x.E, y.g, Eg);
+#pragma unroll
+  for (int i = 0; i < N; ++i) o.g[i] = Eg[i] + x.g[i];
+  R EL[N][N];
+  mm<N, N, N, R>(x.E, y.L, EL);
+  sym_xyt_plus<N, N, S>(EL, x.E, x.L, o.L);
+  return o;
+}
+
+// Lemma 2 with a right operand whose E is zero (any suffix that ends at T,
+// since E_T = 0): only (g, L) is formed.  (g, L) is the smoothed
+// mean/covariance of the suffix; on return it holds a (x) (0, g, L).
+template <int N, class P>
+KF_DEV void sapply(const SElem<N, typename P::R>& a, typename P::R (&g)[N],
+                   typename P::R (&L)[N][N]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  R Eg[N];
+  mv<N, N, R>(a.E, g, Eg);
+  R EL[N][N];
+  mm<N, N, N, R>(a.E, L, EL);
+#pragma unroll
+  for (int i = 0; i < N; ++i) g[i] = Eg[i] + a.g[i];
+  sym_xyt_plus<N, N, S>(EL, a.E, a.L, L);
+}
+
+// Smoothing element of eq. prts_init1 from the filter result (x, P) at step
+// k < T:  E = P F^T (F P F^T + Q)^{-1}, g = x - E F x, L = P - E F P.
+template <int N, class P, class TF>
+KF_DEV SElem<N, typename P::R> smooth_element(const typename P::R (&x)[N],
+                                              const typename P::R (&Pm)[N][N],
+                                              const TF (&F)[N][N], const TF (&Q)[N][N]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  S FP[N][N];
+  mm<N, N, N, S>(F, Pm, FP);
+  S Sm[N][N];
+  sym_xyt_plus<N, N, S>(FP, F, Q, Sm);  // F P F^T + Q
+  S dinv[N];
+  chol_factor<N, S>(Sm, dinv);
+  S Et[N][N];  // E^T = S^{-1} F P
+  copy_mat<N, N, S>(FP, Et);
+  chol_solve<N, N, S>(Sm, dinv, Et);
+  SElem<N, R> o;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) o.E[i][j] = R(Et[j][i]);
+  S Fx[N];
+  mv<N, N, S>(F, x, Fx);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    S s = S(x[i]);
+#pragma unroll
+    for (int t = 0; t < N; ++t) s -= Et[t][i] * Fx[t];
+    o.g[i] = R(s);
+  }
+  // L = P - E (F P): symmetric, upper triangle mirrored
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      S s = S(Pm[i][j]);
+#pragma unroll
+      for (int t = 0; t < N; ++t) s -= Et[t][i] * FP[t][j];
+      o.L[i][j] = R(s);
+      o.L[j][i] = R(s);
+    }
+  return o;
+}
+
+// Two-filter combination (eqs. mean_tf_combination, cov_tf_combination):
+// x_s = (I + P J)^{-1}(x + P eta), P_s = (I + P J)^{-1} P, symmetrised by
+// averaging with its transpose.
+template <int N, class P>
+KF_DEV void tf_combine(const typename P::R (&x)[N], const typename P::R (&Pm)[N][N],
+                       const typename P::R (&eta)[N], const typename P::R (&J)[N][N],
+                       typename P::R (&xs)[N], typename P::R (&Ps)[N][N]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  S M[N][N];
+  mm<N, N, N, S>(Pm, J, M);
+#pragma unroll
+  for (int i = 0; i < N; ++i) M[i][i] += S(1);
+  int piv[N];
+  S dinv[N];
+  lu_factor<N, S>(M, piv, dinv);
+  S B[N][N + 1];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    S s = S(x[r]);
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      B[r][c] = S(Pm[r][c]);
+      s += S(Pm[r][c]) * S(eta[c]);
+    }
+    B[r][N] = s;
+  }
+  lu_solve<N, N + 1, S>(M, piv, dinv, B);
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    xs[r] = R(B[r][N]);
+#pragma unroll
+    for (int c = r; c < N; ++c) {
+      S s = S(0.5) * (B[r][c] + B[c][r]);
+      Ps[r][c] = R(s);
+      Ps[c][r] = R(s);
+    }
+  }
+}
+
+}  // namespace kfs

@@ -1,0 +1,234 @@
+"""Python binding of the C ABI in include/kfscan.h (argument marshalling only).
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+filter and smoothers runs in the HIP kernels of libkfscan.so.  There is no
+CPU path: if the library is missing, or a tensor is not on a GPU, the call
+raises.
+
+    m_f, P_f = filter(model, y)
+    m_f, P_f, m_s, P_s = smooth_rts(model, y)
+    m_f, P_f, m_s, P_s = smooth_twofilter(model, y)
+
+``model`` is any object with tensor attributes F, Q, H, R, m0, P0 (or a tuple
+in that order); ``y`` is ``[T, ny]`` or ``[nseq, T, ny]``.  ``precision`` is
+"f64", "f32" or "mixed" (FP32 storage with FP64 solves, KF_PREC_F32_F64SOLVE).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkfscan.so")
+
+KF_OK, KF_ERR_INVALID_ARG, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE, KF_ERR_DEVICE = range(5)
+PRECISIONS = {"f64": 0, "f32": 1, "mixed": 2}
+SCANS = {"auto": 0, "lookback": 1, "blelloch": 2, "hillis_steele": 3}
+_VOIDP = ctypes.c_void_p
+
+
+class KfProblem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("scan", ctypes.c_int32),
+                ("T", ctypes.c_int64), ("nseq", ctypes.c_int64),
+                ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
+                ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
+                ("m_filt", _VOIDP), ("P_filt", _VOIDP),
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+
+
+class KfScanError(RuntimeError):
+    pass
+
+
+_lib = None
+_lock = threading.Lock()
+EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_size",
+           "kf_workspace_clear", "kf_workspace_timed_out", "kf_filter", "kf_smooth_rts",
+           "kf_smooth_twofilter")
+# When set (the tests set it), every call synchronises and checks the
+# workspace's look-back timeout flag.
+CHECK = os.environ.get("KFSCAN_CHECK", "0") == "1"
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkfscan.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise KfScanError("%s is not built; run paper_2511_10363_amd.build.build()" % path)
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER(KfProblem)
+        lib.kf_abi_version.restype = ctypes.c_int
+        lib.kf_status_string.restype = ctypes.c_char_p
+        lib.kf_status_string.argtypes = [ctypes.c_int]
+        lib.kf_supported.restype = ctypes.c_int
+        lib.kf_supported.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        lib.kf_workspace_size.restype = ctypes.c_int
+        lib.kf_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        lib.kf_workspace_clear.restype = ctypes.c_int
+        lib.kf_workspace_clear.argtypes = [_VOIDP, ctypes.c_size_t, _VOIDP]
+        lib.kf_workspace_timed_out.restype = ctypes.c_int
+        lib.kf_workspace_timed_out.argtypes = [P, _VOIDP, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_int32), _VOIDP]
+        for name in ("kf_filter", "kf_smooth_rts", "kf_smooth_twofilter"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [P, _VOIDP, ctypes.c_size_t, _VOIDP]
+        _lib = lib
+        return lib
+
+
+def status_string(code: int) -> str:
+    return load_library().kf_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != KF_OK:
+        raise KfScanError("%s: %s (status %d)" % (what, status_string(code), code))
+
+
+def dtype_for(precision: str) -> torch.dtype:
+    return torch.float64 if precision == "f64" else torch.float32
+
+
+def _model_tensors(model):
+    if isinstance(model, (tuple, list)):
+        return tuple(model[:6])
+    return (model.F, model.Q, model.H, model.R, model.m0, model.P0)
+
+
+class Workspace:
+    """Device workspace, grown on demand, one per (device, stream).  Calls on
+    one stream run in order, and each call re-initialises the control words it
+    uses, so reuse needs no clearing."""
+
+    _cache: dict = {}
+
+    @classmethod
+    def get(cls, device: torch.device, stream: int, nbytes: int) -> torch.Tensor:
+        key = (device.index, stream)
+        buf = cls._cache.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+            cls._cache[key] = buf
+        return buf
+
+
+def make_problem(model, y, precision="f32", scan="auto", m_filt=None, P_filt=None,
+                 m_smooth=None, P_smooth=None):
+    """Validate tensors and fill a KfProblem.  Returns (problem, keepalive)."""
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % list(PRECISIONS))
+    if scan not in SCANS:
+        raise ValueError("scan must be one of %s" % list(SCANS))
+    dt = dtype_for(precision)
+    F, Q, H, R, m0, P0 = _model_tensors(model)
+    if y.dim() == 2:
+        y = y.unsqueeze(0)
+    if y.dim() != 3:
+        raise ValueError("y must be [T, ny] or [nseq, T, ny]")
+    nseq, T, ny = y.shape
+    nx = F.shape[-1]
+    dev = y.device
+    if dev.type != "cuda":
+        raise KfScanError("kfscan runs on the GPU only; y is on %s" % dev)
+    shapes = {"F": (F, (nx, nx)), "Q": (Q, (nx, nx)), "H": (H, (ny, nx)), "R": (R, (ny, ny)),
+              "m0": (m0, (nx,)), "P0": (P0, (nx, nx))}
+    for name, (t, shp) in shapes.items():
+        if tuple(t.shape) != shp:
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shp))
+        if t.device != dev or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dt, dev))
+    if y.dtype != dt or not y.is_contiguous():
+        raise ValueError("y must be a contiguous %s tensor" % dt)
+    if m_filt is None:
+        m_filt = torch.empty((nseq, T, nx), dtype=dt, device=dev)
+    if P_filt is None:
+        P_filt = torch.empty((nseq, T, nx, nx), dtype=dt, device=dev)
+    p = KfProblem()
+    p.nx, p.ny, p.precision, p.scan = nx, ny, PRECISIONS[precision], SCANS[scan]
+    p.T, p.nseq = T, nseq
+    p.F, p.Q, p.H, p.R = F.data_ptr(), Q.data_ptr(), H.data_ptr(), R.data_ptr()
+    p.m0, p.P0, p.y = m0.data_ptr(), P0.data_ptr(), y.data_ptr()
+    p.m_filt, p.P_filt = m_filt.data_ptr(), P_filt.data_ptr()
+    if m_smooth is not None:
+        p.m_smooth, p.P_smooth = m_smooth.data_ptr(), P_smooth.data_ptr()
+    keep = dict(y=y, m_filt=m_filt, P_filt=P_filt, m_smooth=m_smooth, P_smooth=P_smooth)
+    return p, keep
+
+
+def workspace_size(p: KfProblem) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().kf_workspace_size(ctypes.byref(p), ctypes.byref(n)), "kf_workspace_size")
+    return n.value
+
+
+def _call(entry: str, p: KfProblem, device: torch.device, workspace=None):
+    lib = load_library()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    need = workspace_size(p)
+    ws = workspace if workspace is not None else Workspace.get(device, stream, need)
+    if ws.numel() * ws.element_size() < need:
+        raise KfScanError("workspace of %d bytes is smaller than the %d needed"
+                          % (ws.numel() * ws.element_size(), need))
+    nbytes = ws.numel() * ws.element_size()
+    _check(getattr(lib, entry)(ctypes.byref(p), ws.data_ptr(), nbytes, stream), entry)
+    if CHECK:
+        flag = ctypes.c_int32(0)
+        _check(lib.kf_workspace_timed_out(ctypes.byref(p), ws.data_ptr(), nbytes,
+                                          ctypes.byref(flag), stream), "kf_workspace_timed_out")
+        if flag.value:
+            raise KfScanError("%s: a look-back wait timed out; outputs are invalid" % entry)
+
+
+def _squeeze(x, was2d):
+    return x[0] if was2d else x
+
+
+def filter(model, y, precision="f32", scan="auto", workspace=None):  # noqa: A001
+    """Algorithm 5.  Returns (x_{k|k}, P_{k|k})."""
+    was2d = y.dim() == 2
+    p, keep = make_problem(model, y, precision, scan)
+    _call("kf_filter", p, y.device, workspace)
+    return _squeeze(keep["m_filt"], was2d), _squeeze(keep["P_filt"], was2d)
+
+
+def _smoother(entry, model, y, precision, scan, workspace):
+    was2d = y.dim() == 2
+    yy = y.unsqueeze(0) if was2d else y
+    nseq, T, _ = yy.shape
+    nx = _model_tensors(model)[0].shape[-1]
+    dt = dtype_for(precision)
+    m_s = torch.empty((nseq, T, nx), dtype=dt, device=y.device)
+    P_s = torch.empty((nseq, T, nx, nx), dtype=dt, device=y.device)
+    p, keep = make_problem(model, yy, precision, scan, m_smooth=m_s, P_smooth=P_s)
+    _call(entry, p, y.device, workspace)
+    return tuple(_squeeze(keep[k], was2d) for k in ("m_filt", "P_filt", "m_smooth", "P_smooth"))
+
+
+def smooth_rts(model, y, precision="f32", scan="auto", workspace=None):
+    """Algorithm 6.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
+    return _smoother("kf_smooth_rts", model, y, precision, scan, workspace)
+
+
+def smooth_twofilter(model, y, precision="f32", scan="auto", workspace=None):
+    """Algorithm 7.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
+    return _smoother("kf_smooth_twofilter", model, y, precision, scan, workspace)
+
+
+def supported(nx: int, ny: int, precision: str = "f32") -> bool:
+    return bool(load_library().kf_supported(nx, ny, PRECISIONS[precision]))
+
+
+def model_to_device(model, precision="f32", device="cuda"):
+    """Copy numpy/torch model arrays to contiguous device tensors of the
+    precision's storage dtype.  Returns a tuple (F, Q, H, R, m0, P0)."""
+    dt = dtype_for(precision)
+    return tuple(torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+                 for a in _model_tensors(model))

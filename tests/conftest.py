@@ -4,6 +4,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+os.environ.setdefault("KFSCAN_CHECK", "1")
 
 
 def pytest_configure(config):
