@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: parallel filter + RTS smoother steps/s at nx = 4, T = 2^20.
+
+One "step" of the benchmark loop is one whole pass of the hot path -- the
+parallel Kalman filter (Algorithm 5) and the RTS smoother (Algorithm 6) -- over
+one synthetic constant-velocity tracking sequence of T = 2^20 measurements
+already resident in HBM.  `value` is time steps (measurements) processed per
+second: T * K / wall time of K passes.
+
+Each pass is enqueued stage by stage (kf_prepare, kf_pass_filter,
+kf_pass_rts) with HIP events between the stages on the launch stream, so the
+per-kernel durations used for the roofline come from the timed region itself.
+The CPU baseline times the FP64 sequential oracle (filter + RTS) on this
+machine's host, one core, on the same input.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VALU_PEAK = 157.3e12      # MI355X vector FP32 (published, packed) FLOP/s
+FP64_VALU_PEAK = 78.6e12       # MI355X vector FP64 FLOP/s
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_10363_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json),
+    only if the kernel sources have not changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get("%s|%s|%s" % (kernel, workload, precision))
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f32", choices=["f32", "mixed", "f64"])
+    ap.add_argument("--log2T", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time for the oracle baseline (0 = skip)")
+    ap.add_argument("--seed", type=int, default=20251110)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import kf_workloads as W
+    from paper_2511_10363_amd import kfscan
+
+    kfscan.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    T = 1 << args.log2T
+    prec = args.precision
+    n, m = 4, 2
+    w = 8 if prec == "f64" else 4
+
+    model, y_np = W.tracking(T, seed=args.seed)
+    dt = kfscan.dtype_for(prec)
+    dmodel = kfscan.model_to_device(model.arrays(), prec, dev)
+    y = torch.as_tensor(y_np).to(dev, dt).contiguous()
+    plan = kfscan.Plan(dmodel, y, precision=prec, smoother=True)
+
+    def one_pass(evs=None):
+        if evs is not None:
+            evs[0].record()
+        plan("kf_prepare")
+        if evs is not None:
+            evs[1].record()
+        plan("kf_pass_filter")
+        if evs is not None:
+            evs[2].record()
+        plan("kf_pass_rts")
+        if evs is not None:
+            evs[3].record()
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        one_pass(events[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    wall = t1 - t0
+    ms_per_step = wall / K * 1e3
+    value = T * K / wall
+    lat = np.array([e[0].elapsed_time(e[3]) for e in events])          # ms per whole pass
+    t_prep = np.array([e[0].elapsed_time(e[1]) for e in events])
+    t_filt = np.array([e[1].elapsed_time(e[2]) for e in events])
+    t_rts = np.array([e[2].elapsed_time(e[3]) for e in events])
+
+    # algorithmic bytes per launch: forward pass reads y and writes the filter
+    # moments, the RTS pass writes the smoothed moments; their sum is the
+    # job's compulsory traffic w (m + 2n + 2n^2) per step
+    bytes_filter = T * w * (m + n + n * n)
+    bytes_rts = T * w * (n + n * n)
+    kern = {"k_filter": (float(t_filt.mean()), bytes_filter),
+            "k_rts": (float(t_rts.mean()), bytes_rts)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_bytes = kern[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = load_traffic(dom, "tracking_T2^%d" % args.log2T, prec)
+
+    # accuracy of this run against the FP64 oracle, and the CPU baseline
+    m_f, P_f, m_s, P_s = (t[0].double().cpu().numpy() for t in plan.outputs())
+    cpu = None
+    errors = None
+    if args.cpu_seconds > 0:
+        import oracle
+        arrs = model.arrays()
+        yy = y_np
+        if prec != "f64":
+            cast = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+            arrs = tuple(cast(a) for a in arrs)
+            yy = cast(y_np)
+        reps = 0
+        c0 = time.perf_counter()
+        while True:
+            ref = oracle.smooth_rts(*arrs, yy)
+            reps += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        c1 = time.perf_counter()
+        cpu = {"value": T * reps / (c1 - c0), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": "sequential FP64 filter + RTS smoother over the full T=2^%d input, "
+                         "%d repetition(s)" % (args.log2T, reps)}
+
+        def nw(a, r):
+            return float(np.max(np.abs(a - r)) / max(np.max(np.abs(r)), 1e-300))
+        z = float(np.max(np.abs(m_s - ref[2]) / np.sqrt(np.einsum("kii->ki", ref[3]))))
+        errors = {"m_filt": nw(m_f, ref[0]), "P_filt": nw(P_f, ref[1]),
+                  "m_smooth": nw(m_s, ref[2]), "P_smooth": nw(P_s, ref[3]),
+                  "z_smooth_max": z}
+
+    out = {
+        "metric": "filter+smoother steps/s at nx=4,T=2^20 (% HBM roofline)",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "cv_tracking_nx4_ny2_T2^%d" % args.log2T, "T": T, "nx": n, "ny": m,
+                   "dt": 0.1, "q": 1.0, "r": 0.25, "sequences": 1,
+                   "pipeline": "kf_prepare+kf_pass_filter+kf_pass_rts",
+                   "scan": "lookback", "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom},
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "kernel_ms": {"k_prepare": float(t_prep.mean()), "k_filter": float(t_filt.mean()),
+                      "k_rts": float(t_rts.mean())},
+        "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
+        "errors_vs_oracle": errors,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -135,6 +135,30 @@ kf_status kf_smooth_rts(const kf_problem *p, void *workspace, size_t workspace_b
 kf_status kf_smooth_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* ---- Stage entry points ------------------------------------------------
+ * For callers that schedule or time the passes themselves.  Each enqueues
+ * exactly one kernel on `stream`:
+ *   kf_prepare        derives the element constants of eqs. pkf_init1..3
+ *                     from the model (FP64) into the workspace and zeroes the
+ *                     workspace's control words;
+ *   kf_pass_filter    the forward scan of Algorithm 5 (writes m_filt, P_filt);
+ *   kf_pass_rts       the reverse scan of Algorithm 6 (reads m_filt, P_filt,
+ *                     writes m_smooth, P_smooth);
+ *   kf_pass_twofilter the backward scan and combination of Algorithm 7 (reads
+ *                     y, m_filt, P_filt, writes m_smooth, P_smooth).
+ * A pass needs a kf_prepare of the same problem earlier in stream order on
+ * the same workspace; each pass leaves its own control words zeroed, so
+ * passes may be repeated after one kf_prepare.
+ * kf_filter = kf_prepare + kf_pass_filter;
+ * kf_smooth_rts = kf_prepare + kf_pass_filter + kf_pass_rts;
+ * kf_smooth_twofilter = kf_prepare + kf_pass_filter + kf_pass_twofilter. */
+kf_status kf_prepare(const kf_problem *p, void *workspace, size_t workspace_bytes, void *stream);
+kf_status kf_pass_filter(const kf_problem *p, void *workspace, size_t workspace_bytes,
+                         void *stream);
+kf_status kf_pass_rts(const kf_problem *p, void *workspace, size_t workspace_bytes, void *stream);
+kf_status kf_pass_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,21 +38,25 @@ static kf_status check_sizes(const kf_problem* p) {
   return KF_OK;
 }
 
-static kf_status run(Op op, const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
+static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws_bytes,
+                     void* stream) {
   kf_status s = check_sizes(p);
   if (s != KF_OK) return s;
-  if (!p->F || !p->Q || !p->H || !p->R || !p->m0 || !p->P0 || !p->y || !p->m_filt || !p->P_filt)
+  if ((stages & ST_PREPARE) && (!p->F || !p->Q || !p->H || !p->R || !p->m0 || !p->P0))
     return KF_ERR_INVALID_ARG;
-  if (op != OP_FILTER && (!p->m_smooth || !p->P_smooth)) return KF_ERR_INVALID_ARG;
+  if ((stages & (ST_FORWARD | ST_BACKWARD)) && (!p->y || !p->m_filt || !p->P_filt))
+    return KF_ERR_INVALID_ARG;
+  if (op != OP_FILTER && (stages & ST_BACKWARD) && (!p->m_smooth || !p->P_smooth))
+    return KF_ERR_INVALID_ARG;
   const Layout L = make_layout(p->nx, p->ny, p->precision, p->T, p->nseq);
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
     return KF_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   switch (p->precision) {
-    case KF_PREC_F64: return run_f64(op, *p, w, L, st);
-    case KF_PREC_F32: return run_f32(op, *p, w, L, st);
-    default: return run_mixed(op, *p, w, L, st);
+    case KF_PREC_F64: return run_f64(op, stages, *p, w, L, st);
+    case KF_PREC_F32: return run_f32(op, stages, *p, w, L, st);
+    default: return run_mixed(op, stages, *p, w, L, st);
   }
 }
 
@@ -116,15 +120,31 @@ kf_status kf_workspace_timed_out(const kf_problem* p, const void* ws, size_t ws_
 }
 
 kf_status kf_filter(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
-  return kfs::run(kfs::OP_FILTER, p, ws, ws_bytes, stream);
+  return kfs::run(kfs::OP_FILTER, kfs::ST_ALL, p, ws, ws_bytes, stream);
 }
 
 kf_status kf_smooth_rts(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
-  return kfs::run(kfs::OP_RTS, p, ws, ws_bytes, stream);
+  return kfs::run(kfs::OP_RTS, kfs::ST_ALL, p, ws, ws_bytes, stream);
 }
 
 kf_status kf_smooth_twofilter(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
-  return kfs::run(kfs::OP_TWOFILTER, p, ws, ws_bytes, stream);
+  return kfs::run(kfs::OP_TWOFILTER, kfs::ST_ALL, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_prepare(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run(kfs::OP_FILTER, kfs::ST_PREPARE, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_pass_filter(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run(kfs::OP_FILTER, kfs::ST_FORWARD, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_pass_rts(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run(kfs::OP_RTS, kfs::ST_BACKWARD, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_pass_twofilter(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run(kfs::OP_TWOFILTER, kfs::ST_BACKWARD, p, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

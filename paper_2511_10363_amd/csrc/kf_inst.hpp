@@ -7,17 +7,19 @@
 namespace kfs {
 
 template <int N, int M, class P>
-kf_status run_shape(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
+kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                    hipStream_t st) {
   using R = typename P::R;
   constexpr int B = kBlock;
   constexpr int IT = items_per_thread(N);
   R* cst = reinterpret_cast<R*>(ws + L.cst);
   const size_t prep_blocks = (L.ctrl_words + 255) / 256;
-  hipLaunchKernelGGL((k_prepare<N, M, R>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
-                     dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
-                     static_cast<const R*>(p.H), static_cast<const R*>(p.R),
-                     static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
-                     reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+  if (stages & ST_PREPARE)
+    hipLaunchKernelGGL((k_prepare<N, M, R>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
+                       dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                       static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                       static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
+                       reinterpret_cast<unsigned*>(ws), L.ctrl_words);
   const unsigned grid = (unsigned)(L.ntiles * p.nseq);
   auto args = [&](int slot) {
     ScanArgs<R> a{};
@@ -35,8 +37,9 @@ kf_status run_shape(Op op, const kf_problem& p, char* ws, const Layout& L, hipSt
   ScanArgs<R> fa = args(0);
   fa.m_out = static_cast<R*>(p.m_filt);
   fa.P_out = static_cast<R*>(p.P_filt);
-  hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, fa);
-  if (op != OP_FILTER) {
+  if (stages & ST_FORWARD)
+    hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, fa);
+  if (op != OP_FILTER && (stages & ST_BACKWARD)) {
     ScanArgs<R> ba = args(1);
     ba.m_in = static_cast<const R*>(p.m_filt);
     ba.P_in = static_cast<const R*>(p.P_filt);
@@ -62,9 +65,10 @@ kf_status run_shape(Op op, const kf_problem& p, char* ws, const Layout& L, hipSt
   X(4, 4)
 
 template <class P>
-kf_status run_prec(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
+kf_status run_prec(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                   hipStream_t st) {
 #define KFS_CASE(n, m) \
-  if (p.nx == n && p.ny == m) return run_shape<n, m, P>(op, p, ws, L, st);
+  if (p.nx == n && p.ny == m) return run_shape<n, m, P>(op, stages, p, ws, L, st);
   KFS_SHAPES(KFS_CASE)
 #undef KFS_CASE
   return KF_ERR_UNSUPPORTED;

@@ -2,7 +2,8 @@
 #include "kf_inst.hpp"
 
 namespace kfs {
-kf_status run_f64(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
-  return run_prec<PrecF64>(op, p, ws, L, st);
+kf_status run_f64(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                  hipStream_t st) {
+  return run_prec<PrecF64>(op, stages, p, ws, L, st);
 }
 }  // namespace kfs

@@ -2,7 +2,8 @@
 #include "kf_inst.hpp"
 
 namespace kfs {
-kf_status run_mixed(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st) {
-  return run_prec<PrecMixed>(op, p, ws, L, st);
+kf_status run_mixed(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                  hipStream_t st) {
+  return run_prec<PrecMixed>(op, stages, p, ws, L, st);
 }
 }  // namespace kfs

@@ -162,7 +162,7 @@ template <class R> struct ScanArgs {
   int* flags;      // [nseq * ntiles]
   R* agg;          // [nseq * ntiles][elem size]
   R* pre;          // [nseq * ntiles][anchored prefix size]
-  unsigned* ctr;   // [0] tile ticket, [2] look-back timeout flag
+  unsigned* ctr;   // [0] tile ticket, [1] finished blocks, [2] look-back timeout flag
   long T;
   long ntiles;     // tiles per sequence
   long nseq;
@@ -200,6 +200,29 @@ template <int N, class R> struct State {
   R P[N][N];
 };
 
+// After the last block of a scan has finished, clear that scan's status
+// words and tile ticket, so the pass can be enqueued again without another
+// preparation launch.  The timeout flag (ctr[2]) is left for diagnosis.
+template <int BLOCK>
+KF_DEV void finish_grid(int* __restrict__ flags, unsigned* __restrict__ ctr, long nflags,
+                        int* s_last) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned done = atomicAdd(ctr + 1, 1u);
+    *s_last = (done == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (*s_last) {
+    __threadfence();
+    for (long i = threadIdx.x; i < nflags; i += BLOCK) flags[i] = LB_EMPTY;
+    if (threadIdx.x == 0) {
+      ctr[0] = 0u;
+      ctr[1] = 0u;
+    }
+  }
+}
+
 // ===========================================================================
 // Forward filter (Algorithm 5)
 // ===========================================================================
@@ -213,6 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
   __shared__ E s_wt[NW];
   __shared__ R s_pre[PS];
   __shared__ long s_tile;
+  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
   __syncthreads();
@@ -355,6 +379,7 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
       for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.P[r][c];
     }
   }
+  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
 }
 
 // ===========================================================================
@@ -383,6 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
   __shared__ E s_wt[NW];
   __shared__ R s_pre[PS];
   __shared__ long s_tile;
+  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
   __syncthreads();
@@ -547,6 +573,7 @@ __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
       for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.P[r][c];
     }
   }
+  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
 }
 
 // ===========================================================================
@@ -567,6 +594,7 @@ __global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a) 
   __shared__ E s_wt[NW];
   __shared__ R s_pre[PS];
   __shared__ long s_tile;
+  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
   __syncthreads();
@@ -727,6 +755,7 @@ __global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a) 
       for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = Ps[r][c];
     }
   }
+  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
 }
 
 }  // namespace kfs

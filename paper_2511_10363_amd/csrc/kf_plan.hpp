@@ -64,10 +64,16 @@ inline Layout make_layout(int nx, int ny, int precision, long T, long nseq) {
 
 enum Op { OP_FILTER = 0, OP_RTS = 1, OP_TWOFILTER = 2 };
 
+// Which kernels of an operation to enqueue.
+enum Stage { ST_PREPARE = 1, ST_FORWARD = 2, ST_BACKWARD = 4, ST_ALL = 7 };
+
 // Implemented once per precision (kf_inst_*.hip).
-kf_status run_f64(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st);
-kf_status run_f32(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st);
-kf_status run_mixed(Op op, const kf_problem& p, char* ws, const Layout& L, hipStream_t st);
+kf_status run_f64(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                  hipStream_t st);
+kf_status run_f32(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                  hipStream_t st);
+kf_status run_mixed(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+                    hipStream_t st);
 bool shape_built(int nx, int ny);
 
 }  // namespace kfs

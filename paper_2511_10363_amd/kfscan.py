@@ -48,7 +48,9 @@ _lib = None
 _lock = threading.Lock()
 EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_size",
            "kf_workspace_clear", "kf_workspace_timed_out", "kf_filter", "kf_smooth_rts",
-           "kf_smooth_twofilter")
+           "kf_smooth_twofilter", "kf_prepare", "kf_pass_filter", "kf_pass_rts",
+           "kf_pass_twofilter")
+STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
 # When set (the tests set it), every call synchronises and checks the
 # workspace's look-back timeout flag.
 CHECK = os.environ.get("KFSCAN_CHECK", "0") == "1"
@@ -76,7 +78,7 @@ def load_library(path: str = LIB_PATH):
         lib.kf_workspace_timed_out.restype = ctypes.c_int
         lib.kf_workspace_timed_out.argtypes = [P, _VOIDP, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_int32), _VOIDP]
-        for name in ("kf_filter", "kf_smooth_rts", "kf_smooth_twofilter"):
+        for name in ("kf_filter", "kf_smooth_rts", "kf_smooth_twofilter") + STAGES:
             f = getattr(lib, name)
             f.restype = ctypes.c_int
             f.argtypes = [P, _VOIDP, ctypes.c_size_t, _VOIDP]
@@ -220,6 +222,39 @@ def smooth_rts(model, y, precision="f32", scan="auto", workspace=None):
 def smooth_twofilter(model, y, precision="f32", scan="auto", workspace=None):
     """Algorithm 7.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
     return _smoother("kf_smooth_twofilter", model, y, precision, scan, workspace)
+
+
+class Plan:
+    """A problem bound to preallocated device buffers, for repeated calls and
+    for stage-by-stage launches (kf_prepare, kf_pass_*), e.g. to time each
+    kernel with events on the current stream."""
+
+    def __init__(self, model, y, precision="f32", scan="auto", smoother=True, workspace=None):
+        was2d = y.dim() == 2
+        yy = y.unsqueeze(0) if was2d else y
+        nseq, T, _ = yy.shape
+        nx = _model_tensors(model)[0].shape[-1]
+        dt = dtype_for(precision)
+        self.model = model
+        self.m_s = self.P_s = None
+        if smoother:
+            self.m_s = torch.empty((nseq, T, nx), dtype=dt, device=y.device)
+            self.P_s = torch.empty((nseq, T, nx, nx), dtype=dt, device=y.device)
+        self.p, self.keep = make_problem(model, yy, precision, scan, m_smooth=self.m_s,
+                                         P_smooth=self.P_s)
+        self.device = y.device
+        self.need = workspace_size(self.p)
+        self.ws = workspace if workspace is not None else torch.empty(
+            max(self.need, 1 << 20), dtype=torch.uint8, device=y.device)
+        self.lib = load_library()
+
+    def __call__(self, entry: str):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(getattr(self.lib, entry)(ctypes.byref(self.p), self.ws.data_ptr(),
+                                        self.ws.numel(), stream), entry)
+
+    def outputs(self):
+        return (self.keep["m_filt"], self.keep["P_filt"], self.m_s, self.P_s)
 
 
 def supported(nx: int, ny: int, precision: str = "f32") -> bool:
