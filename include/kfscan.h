@@ -80,10 +80,14 @@ typedef enum kf_precision {
 } kf_precision;
 
 typedef enum kf_scan {
-    KF_SCAN_AUTO = 0,          /* library default (single-pass look-back)          */
-    KF_SCAN_LOOKBACK = 1,      /* single-pass tiled scan with decoupled look-back  */
-    KF_SCAN_BLELLOCH = 2,      /* Algorithm 2, one kernel per tree level           */
-    KF_SCAN_HILLIS_STEELE = 3  /* Algorithm 1, one kernel per doubling level       */
+    KF_SCAN_AUTO = 0,             /* library default (KF_SCAN_LOOKBACK)              */
+    KF_SCAN_LOOKBACK = 1,         /* single-pass tiled scan with decoupled look-back;
+                                     the filtering-element scans use the
+                                     time-invariant fold (see below)                 */
+    KF_SCAN_BLELLOCH = 2,         /* Algorithm 2, one kernel per tree level          */
+    KF_SCAN_HILLIS_STEELE = 3,    /* Algorithm 1, one kernel per doubling level      */
+    KF_SCAN_LOOKBACK_GENERIC = 4  /* the look-back scan folding full elements step by
+                                     step, with no use of time invariance            */
 } kf_scan;
 
 typedef struct kf_problem {

@@ -28,13 +28,13 @@ static kf_status check_sizes(const kf_problem* p) {
   if (!p) return KF_ERR_INVALID_ARG;
   if (p->nx < 1 || p->ny < 1 || p->T < 1 || p->nseq < 1) return KF_ERR_INVALID_ARG;
   if (p->precision < KF_PREC_F64 || p->precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
-  if (p->scan < KF_SCAN_AUTO || p->scan > KF_SCAN_HILLIS_STEELE) return KF_ERR_INVALID_ARG;
+  if (p->scan < KF_SCAN_AUTO || p->scan > KF_SCAN_LOOKBACK_GENERIC) return KF_ERR_INVALID_ARG;
   // tile counts and element offsets stay well inside 32-bit grid limits
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   if (!shape_built(p->nx, p->ny)) return KF_ERR_UNSUPPORTED;
   if (p->scan == KF_SCAN_BLELLOCH || p->scan == KF_SCAN_HILLIS_STEELE) return KF_ERR_UNSUPPORTED;
   const Layout L = make_layout(p->nx, p->ny, p->precision, p->T, p->nseq);
-  if ((double)L.ntiles * (double)p->nseq > 2147483647.0) return KF_ERR_INVALID_ARG;
+  if ((double)L.max_tiles * (double)p->nseq > 2147483647.0) return KF_ERR_INVALID_ARG;
   return KF_OK;
 }
 

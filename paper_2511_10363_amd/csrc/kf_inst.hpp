@@ -12,16 +12,17 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
   using R = typename P::R;
   constexpr int B = kBlock;
   constexpr int IT = items_per_thread(N);
+  constexpr int ITI = items_ti(N);
   R* cst = reinterpret_cast<R*>(ws + L.cst);
   const size_t prep_blocks = (L.ctrl_words + 255) / 256;
   if (stages & ST_PREPARE)
-    hipLaunchKernelGGL((k_prepare<N, M, R>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
+    hipLaunchKernelGGL((k_prepare<N, M, R, ITI>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
                        dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
                        static_cast<const R*>(p.H), static_cast<const R*>(p.R),
                        static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
                        reinterpret_cast<unsigned*>(ws), L.ctrl_words);
-  const unsigned grid = (unsigned)(L.ntiles * p.nseq);
-  auto args = [&](int slot) {
+  const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
+  auto args = [&](int slot, int items) {
     ScanArgs<R> a{};
     a.cst = cst;
     a.y = static_cast<const R*>(p.y);
@@ -30,25 +31,30 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
     a.pre = reinterpret_cast<R*>(ws + L.pre[slot]);
     a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
     a.T = p.T;
-    a.ntiles = L.ntiles;
+    a.ntiles = ntiles_for(p.T, items);
     a.nseq = p.nseq;
     return a;
   };
-  ScanArgs<R> fa = args(0);
-  fa.m_out = static_cast<R*>(p.m_filt);
-  fa.P_out = static_cast<R*>(p.P_filt);
-  if (stages & ST_FORWARD)
-    hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, fa);
+  auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
+  if (stages & ST_FORWARD) {
+    ScanArgs<R> fa = args(0, generic ? IT : ITI);
+    fa.m_out = static_cast<R*>(p.m_filt);
+    fa.P_out = static_cast<R*>(p.P_filt);
+    if (generic)
+      hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), grid(fa), dim3(B), 0, st, fa);
+    else
+      hipLaunchKernelGGL((k_filter_ti<N, M, P, B, ITI>), grid(fa), dim3(B), 0, st, fa);
+  }
   if (op != OP_FILTER && (stages & ST_BACKWARD)) {
-    ScanArgs<R> ba = args(1);
+    ScanArgs<R> ba = args(1, IT);
     ba.m_in = static_cast<const R*>(p.m_filt);
     ba.P_in = static_cast<const R*>(p.P_filt);
     ba.m_out = static_cast<R*>(p.m_smooth);
     ba.P_out = static_cast<R*>(p.P_smooth);
     if (op == OP_RTS)
-      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, ba);
+      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba);
     else
-      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), dim3(grid), dim3(B), 0, st, ba);
+      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba);
   }
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }

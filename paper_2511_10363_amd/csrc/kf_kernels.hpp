@@ -27,16 +27,23 @@ namespace kfs {
 //   first element (k = 1): x = F m0, P = F P0 F^T + Q, S1 = H P H^T + R,
 //     K1 = P H^T S1^{-1}, A_1 = 0, b_1 = c1 + K1 y_1 with c1 = x - K1 H x,
 //     C_1 = P - K1 S1 K1^T, eta_1 = W y_1, J_1 = J (reading C4).
-// F and Q are copied for the smoothing elements.  Layout (type R):
-template <int N, int M> struct CL {
+// The model itself (F, Q, H, R, m0, P0) is copied for the per-step updates
+// and the smoothing elements.  For the time-invariant pipelines, SL is the
+// matrix part of an aggregate of L consecutive generic elements and
+// PHI[i], PSI[i] (i < L) map y at the i-th step of such an aggregate to its
+// vector part:  b = sum_i PHI[i] y_i,  eta = sum_i PSI[i] y_i.
+// Layout (type R):
+template <int N, int M, int L = 1> struct CL {
   static constexpr int A = 0, C = A + N * N, J = C + N * N, K = J + N * N, W = K + N * M,
                        K1 = W + N * M, c1 = K1 + N * M, C1 = c1 + N, F = C1 + N * N,
-                       Q = F + N * N, SIZE = Q + N * N;
+                       Q = F + N * N, H = Q + N * N, Rm = H + M * N, m0 = Rm + M * M,
+                       P0 = m0 + N, SL = P0 + N * N, PHI = SL + 3 * N * N,
+                       PSI = PHI + L * N * M, SIZE = PSI + L * N * M;
 };
 
-// The same launch zeroes the workspace's control words (tile tickets,
-// timeout flags, look-back status words) with a grid-stride loop.
-template <int N, int M, class R>
+// The preparation launch also zeroes the workspace's control words (tile
+// tickets, timeout flags, look-back status words) with a grid-stride loop.
+template <int N, int M, class R, int L>
 __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const R* __restrict__ Q_,
                                                  const R* __restrict__ H_, const R* __restrict__ R_,
                                                  const R* __restrict__ m0_,
@@ -45,109 +52,201 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ctrl_words;
        i += (size_t)gridDim.x * blockDim.x)
     ctrl[i] = 0u;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
   using D = double;
-  using L = CL<N, M>;
-  D F[N][N], Q[N][N], H[M][N], Rm[M][M], m0[N], P0[N][N];
+  using LY = CL<N, M, L>;
+  __shared__ MPart<N, D> sS[L + 1];  // sS[j]: matrix part of j consecutive generic elements
+  __shared__ D sP[L][4][N][N];       // vector coefficients of sS[i] (x) sS[1]
+  __shared__ D sK[N][M], sW[N][M];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    D F[N][N], Q[N][N], H[M][N], Rm[M][M], m0[N], P0[N][N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    m0[i] = D(m0_[i]);
+    for (int i = 0; i < N; ++i) {
+      m0[i] = D(m0_[i]);
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      F[i][j] = D(F_[i * N + j]);
-      Q[i][j] = D(Q_[i * N + j]);
-      P0[i][j] = D(P0_[i * N + j]);
+      for (int j = 0; j < N; ++j) {
+        F[i][j] = D(F_[i * N + j]);
+        Q[i][j] = D(Q_[i * N + j]);
+        P0[i][j] = D(P0_[i * N + j]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) H[i][j] = D(H_[i * N + j]);
+#pragma unroll
+      for (int j = 0; j < M; ++j) Rm[i][j] = D(R_[i * M + j]);
+    }
+    // generic element
+    D HQ[M][N], S[M][M], sd[M];
+    mm<M, N, N, D>(H, Q, HQ);
+    sym_xyt_plus<M, N, D>(HQ, H, Rm, S);
+    chol_factor<M, D>(S, sd);
+    D Kt[M][N];  // K^T = S^{-1} H Q
+    copy_mat<M, N, D>(HQ, Kt);
+    chol_solve<M, N, D>(S, sd, Kt);
+    D IKH[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        D s = (i == j) ? D(1) : D(0);
+#pragma unroll
+        for (int t = 0; t < M; ++t) s -= Kt[t][i] * H[t][j];
+        IKH[i][j] = s;
+      }
+    D A[N][N], C[N][N];
+    mm<N, N, N, D>(IKH, F, A);
+    mm<N, N, N, D>(IKH, Q, C);
+    D HF[M][N], Wt[M][N];  // W^T = S^{-1} H F
+    mm<M, N, N, D>(H, F, HF);
+    copy_mat<M, N, D>(HF, Wt);
+    chol_solve<M, N, D>(S, sd, Wt);
+    D Jm[N][N];
+    D Z[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Z[i][j] = D(0);
+    sym_xty_plus<N, M, D>(Wt, HF, Z, Jm);  // J = (S^{-1} H F)^T (H F)
+    // first element
+    D x[N], FP[N][N], P[N][N];
+    mv<N, N, D>(F, m0, x);
+    mm<N, N, N, D>(F, P0, FP);
+    sym_xyt_plus<N, N, D>(FP, F, Q, P);
+    D HP[M][N], S1[M][M], s1d[M];
+    mm<M, N, N, D>(H, P, HP);
+    sym_xyt_plus<M, N, D>(HP, H, Rm, S1);
+    chol_factor<M, D>(S1, s1d);
+    D K1t[M][N];
+    copy_mat<M, N, D>(HP, K1t);
+    chol_solve<M, N, D>(S1, s1d, K1t);
+    D Hx[M], c1[N], C1[N][N];
+    mv<M, N, D>(H, x, Hx);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      D s = x[i];
+#pragma unroll
+      for (int t = 0; t < M; ++t) s -= K1t[t][i] * Hx[t];
+      c1[i] = s;
+    }
+    // C_1 = P - K1 S1 K1^T = P - (H P)^T S1^{-1} (H P)
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        D s = P[i][j];
+#pragma unroll
+        for (int t = 0; t < M; ++t) s -= HP[t][i] * K1t[t][j];
+        C1[i][j] = s;
+        C1[j][i] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      cst[LY::c1 + i] = R(c1[i]);
+      cst[LY::m0 + i] = R(m0[i]);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const D Cs = 0.5 * (C[i][j] + C[j][i]);
+        cst[LY::A + i * N + j] = R(A[i][j]);
+        cst[LY::C + i * N + j] = R(Cs);
+        cst[LY::J + i * N + j] = R(Jm[i][j]);
+        cst[LY::C1 + i * N + j] = R(C1[i][j]);
+        cst[LY::F + i * N + j] = R(F[i][j]);
+        cst[LY::Q + i * N + j] = R(0.5 * (Q[i][j] + Q[j][i]));
+        cst[LY::P0 + i * N + j] = R(0.5 * (P0[i][j] + P0[j][i]));
+        sS[1].A[i][j] = A[i][j];
+        sS[1].C[i][j] = Cs;
+        sS[1].J[i][j] = Jm[i][j];
+      }
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        cst[LY::K + i * M + t] = R(Kt[t][i]);
+        cst[LY::W + i * M + t] = R(Wt[t][i]);
+        cst[LY::K1 + i * M + t] = R(K1t[t][i]);
+        sK[i][t] = Kt[t][i];
+        sW[i][t] = Wt[t][i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) cst[LY::H + i * N + j] = R(H[i][j]);
+#pragma unroll
+      for (int j = 0; j < M; ++j) cst[LY::Rm + i * M + j] = R(0.5 * (Rm[i][j] + Rm[j][i]));
     }
   }
-#pragma unroll
-  for (int i = 0; i < M; ++i) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) H[i][j] = D(H_[i * N + j]);
-#pragma unroll
-    for (int j = 0; j < M; ++j) Rm[i][j] = D(R_[i * M + j]);
+  __syncthreads();
+  // matrix parts of 2..L consecutive generic elements by doubling:
+  // sS[h + i] = sS[h] (x) sS[i] for 1 <= i <= h
+  for (int h = 1; h < L; h *= 2) {
+    if (tid >= 1 && tid <= h && h + tid <= L) {
+      D P1[N][N], P2[N][N], P3[N][N], P4[N][N];
+      MPart<N, D> o;
+      mpart_combine<N, D>(sS[h], sS[tid], o, P1, P2, P3, P4);
+      sS[h + tid] = o;
+    }
+    __syncthreads();
   }
-  // generic element
-  D HQ[M][N], S[M][M], sd[M];
-  mm<M, N, N, D>(H, Q, HQ);
-  sym_xyt_plus<M, N, D>(HQ, H, Rm, S);
-  chol_factor<M, D>(S, sd);
-  D Kt[M][N];  // K^T = S^{-1} H Q
-  copy_mat<M, N, D>(HQ, Kt);
-  chol_solve<M, N, D>(S, sd, Kt);
-  D IKH[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      D s = (i == j) ? D(1) : D(0);
-#pragma unroll
-      for (int t = 0; t < M; ++t) s -= Kt[t][i] * H[t][j];
-      IKH[i][j] = s;
-    }
-  D A[N][N], C[N][N];
-  mm<N, N, N, D>(IKH, F, A);
-  mm<N, N, N, D>(IKH, Q, C);
-  D HF[M][N], Wt[M][N];  // W^T = S^{-1} H F
-  mm<M, N, N, D>(H, F, HF);
-  copy_mat<M, N, D>(HF, Wt);
-  chol_solve<M, N, D>(S, sd, Wt);
-  D Jm[N][N];
-  D Z[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) Z[i][j] = D(0);
-  sym_xty_plus<N, M, D>(Wt, HF, Z, Jm);  // J = (S^{-1} H F)^T (H F)
-  // first element
-  D x[N], FP[N][N], P[N][N];
-  mv<N, N, D>(F, m0, x);
-  mm<N, N, N, D>(F, P0, FP);
-  sym_xyt_plus<N, N, D>(FP, F, Q, P);
-  D HP[M][N], S1[M][M], s1d[M];
-  mm<M, N, N, D>(H, P, HP);
-  sym_xyt_plus<M, N, D>(HP, H, Rm, S1);
-  chol_factor<M, D>(S1, s1d);
-  D K1t[M][N];
-  copy_mat<M, N, D>(HP, K1t);
-  chol_solve<M, N, D>(S1, s1d, K1t);
-  D Hx[M], c1[N], C1[N][N];
-  mv<M, N, D>(H, x, Hx);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    D s = x[i];
-#pragma unroll
-    for (int t = 0; t < M; ++t) s -= K1t[t][i] * Hx[t];
-    c1[i] = s;
+  // vector coefficients of sS[i] (x) sS[1], i = 1 .. L-1
+  if (tid >= 1 && tid < L) {
+    D P1[N][N], P2[N][N], P3[N][N], P4[N][N];
+    MPart<N, D> o;
+    mpart_combine<N, D>(sS[tid], sS[1], o, P1, P2, P3, P4);
+    copy_mat<N, N, D>(P1, sP[tid][0]);
+    copy_mat<N, N, D>(P2, sP[tid][1]);
+    copy_mat<N, N, D>(P3, sP[tid][2]);
+    copy_mat<N, N, D>(P4, sP[tid][3]);
   }
-  // C_1 = P - K1 S1 K1^T = P - (H P)^T S1^{-1} (H P)
+  __syncthreads();
+  // coefficient of y_j in the L-aggregate: step j enters as (K y_j, W y_j)
+  // when j = 0, else through sS[j] (x) sS[1]; every later step i then maps
+  // eta <- eta - P4(i) b and b <- P1(i) b
+  if (tid < L) {
+    const int j = tid;
+    D Bc[N][M], Ec[N][M];
+    if (j == 0) {
+      copy_mat<N, M, D>(sK, Bc);
+      copy_mat<N, M, D>(sW, Ec);
+    } else {
+      D PW[N][M];
+      mm<N, N, M, D>(sP[j][1], sW, PW);
 #pragma unroll
-  for (int i = 0; i < N; ++i)
+      for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int j = i; j < N; ++j) {
-      D s = P[i][j];
+        for (int c = 0; c < M; ++c) Bc[r][c] = PW[r][c] + sK[r][c];
+      mm<N, N, M, D>(sP[j][2], sW, Ec);
+    }
+    for (int i = j + 1; i < L; ++i) {
+      D T1[N][M], T2[N][M];
+      mm<N, N, M, D>(sP[i][3], Bc, T1);
+      mm<N, N, M, D>(sP[i][0], Bc, T2);
 #pragma unroll
-      for (int t = 0; t < M; ++t) s -= HP[t][i] * K1t[t][j];
-      C1[i][j] = s;
-      C1[j][i] = s;
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          Ec[r][c] -= T1[r][c];
+          Bc[r][c] = T2[r][c];
+        }
     }
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    cst[L::c1 + i] = R(c1[i]);
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      cst[L::A + i * N + j] = R(A[i][j]);
-      cst[L::C + i * N + j] = R(0.5 * (C[i][j] + C[j][i]));
-      cst[L::J + i * N + j] = R(Jm[i][j]);
-      cst[L::C1 + i * N + j] = R(C1[i][j]);
-      cst[L::F + i * N + j] = R(F[i][j]);
-      cst[L::Q + i * N + j] = R(0.5 * (Q[i][j] + Q[j][i]));
-    }
+      for (int c = 0; c < M; ++c) {
+        cst[LY::PHI + j * N * M + r * M + c] = R(Bc[r][c]);
+        cst[LY::PSI + j * N * M + r * M + c] = R(Ec[r][c]);
+      }
+  }
+  if (tid == 0) {
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-      cst[L::K + i * M + t] = R(Kt[t][i]);
-      cst[L::W + i * M + t] = R(Wt[t][i]);
-      cst[L::K1 + i * M + t] = R(K1t[t][i]);
-    }
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        cst[LY::SL + i * N + j] = R(sS[L].A[i][j]);
+        cst[LY::SL + N * N + i * N + j] = R(sS[L].C[i][j]);
+        cst[LY::SL + 2 * N * N + i * N + j] = R(sS[L].J[i][j]);
+      }
   }
 }
 
@@ -195,11 +294,6 @@ KF_DEV FElem<N, R> filter_element(const R* __restrict__ cst, long k, const R (&y
   return a;
 }
 
-template <int N, class R> struct State {
-  R x[N];
-  R P[N][N];
-};
-
 // After the last block of a scan has finished, clear that scan's status
 // words and tile ticket, so the pass can be enqueued again without another
 // preparation launch.  The timeout flag (ctr[2]) is left for diagnosis.
@@ -224,17 +318,61 @@ KF_DEV void finish_grid(int* __restrict__ flags, unsigned* __restrict__ ctr, lon
 }
 
 // ===========================================================================
-// Forward filter (Algorithm 5)
+// Generic tile driver shared by the three scans.
+//
+// A pipeline P supplies, in scan order:
+//   E                   element type; op(p, q) the scan-order combine
+//   St                  anchored state (two arrays, v[N] and m[N][N]), the part
+//                       of an anchored prefix/suffix the outputs need
+//   fold(k0, tid)       the thread's aggregate over its L steps
+//   apply(st, e)        st := st (x) e  (forward)   or  e (x) st  (reverse)
+//   expand(st, e)       element form of an anchored state, for the look-back
+//   anchor(e, st)       anchored state of an anchored element
+//   initial(st)         the anchored state before tile 0 (scan order)
+//   steps(k0, st)       apply the state step by step and write the outputs
+// Tile 0 in scan order starts from initial(); it is the prior (m0, P0) for
+// the time-invariant filter and the zero state elsewhere, which the anchored
+// element inside tile 0 (step 1 for the filter, step T for the reverse
+// scans) overwrites.
 // ===========================================================================
-template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
-  using R = typename P::R;
-  using E = FElem<N, R>;
+template <int N, class R> struct St {
+  R v[N];
+  R m[N][N];
+};
+
+template <int N, class R> KF_DEV void st_zero(St<N, R>& s) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    s.v[i] = R(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s.m[i][j] = R(0);
+  }
+}
+template <int N, class R> KF_DEV void st_load(St<N, R>& s, const R* p) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    s.v[i] = p[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) s.m[i][j] = p[N + i * N + j];
+  }
+}
+template <int N, class R> KF_DEV void st_store(R* p, const St<N, R>& s) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    p[i] = s.v[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[N + i * N + j] = s.m[i][j];
+  }
+}
+
+template <class Pipe, int N, class R, int BLOCK, int L>
+KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
+  using E = typename Pipe::E;
   constexpr int NW = BLOCK / WAVE;
-  constexpr int TILE = BLOCK * L;
-  constexpr int PS = N + N * N;  // anchored prefix payload: (b, C)
-  __shared__ E s_wt[NW];
-  __shared__ R s_pre[PS];
+  constexpr int PS = N + N * N;
+  __shared__ E s_wt[NW];      // inclusive totals of each wavefront
+  __shared__ E s_x[BLOCK];    // inclusive prefix of each thread within its wavefront
+  __shared__ R s_pre[PS];     // the tile's exclusive anchored state
   __shared__ long s_tile;
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
@@ -242,60 +380,31 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
   __syncthreads();
   const long gt = s_tile;
   const long seq = gt / a.ntiles, t = gt - seq * a.ntiles;
-  const long k0 = t * TILE + (long)tid * L;
-  const R* __restrict__ y = a.y + seq * a.T * M;
-  const R* __restrict__ cst = a.cst;
-  auto op = [](const E& p, const E& q) { return fcombine<N, P>(p, q); };
+  pp.bind(seq, t, tid);
+  auto op = [&](const E& p, const E& q) { return pp.op(p, q); };
 
   // 1. thread fold
-  R yv[L][M];
-#pragma unroll
-  for (int i = 0; i < L; ++i)
-#pragma unroll
-    for (int c = 0; c < M; ++c) yv[i][c] = (k0 + i < a.T) ? y[(k0 + i) * M + c] : R(0);
-  E agg;
-  if (k0 < a.T) {
-    agg = filter_element<N, M, R>(cst, k0, yv[0]);
-  } else {
-    set_identity(agg);
+  {
+    E x = pp.fold();
+    // 2. wavefront scan, results through LDS
+    wave_inclusive_scan(x, lane, op);
+    s_x[tid] = x;
+    if (lane == WAVE - 1) s_wt[wid] = x;
   }
-#pragma unroll
-  for (int i = 1; i < L; ++i) {
-    if (k0 + i < a.T) agg = op(agg, filter_element<N, M, R>(cst, k0 + i, yv[i]));
-  }
-
-  // 2. workgroup scan
-  E x = agg;
-  wave_inclusive_scan(x, lane, op);
-  if (lane == WAVE - 1) s_wt[wid] = x;
-  E lex = shfl_up(x, 1);
   __syncthreads();
-  E tex;  // exclusive prefix of this thread within the tile (valid if tid > 0)
-  if (wid > 0) {
-    E wex = s_wt[0];
-#pragma unroll 1
-    for (int w = 1; w < wid; ++w) wex = op(wex, s_wt[w]);
-    tex = (lane > 0) ? op(wex, lex) : wex;
-  } else {
-    tex = lex;
-  }
 
-  // 3. publish + look-back (wave 0)
+  // 3. publish the tile aggregate, look back, publish the anchored prefix
   const long base = seq * a.ntiles;
   if (wid == 0) {
     E tot = s_wt[0];
 #pragma unroll 1
     for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
     if (t == 0) {
-      // tile 0 holds step 1 (A_1 = 0): its aggregate is the anchored prefix
       if (lane == 0) {
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = tot.b[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = tot.C[i][j];
-        }
+        St<N, R> st;
+        pp.initial(st);
+        pp.apply(st, tot);
+        st_store(a.pre + (base + t) * PS, st);
         lb_store_flag(a.flags + base + t, LB_PREFIX);
       }
     } else {
@@ -305,88 +414,249 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
       }
       auto load_agg = [&](long idx, E& v) { gload(v, a.agg + (base + idx) * E::SIZE); };
       auto expand = [&](long idx, E& v) {
-        const R* p = a.pre + (base + idx) * PS;
-        set_identity(v);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          v.A[i][i] = R(0);
-          v.b[i] = p[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) v.C[i][j] = p[N + i * N + j];
-        }
+        St<N, R> st;
+        st_load(st, a.pre + (base + idx) * PS);
+        pp.expand(st, v);
       };
       E ex = lookback<E>(a.flags + base, a.ctr + 2, t, lane, op, load_agg, expand);
       if (lane == 0) {
-        State<N, R> st;
-        copy_vec<N, R>(ex.b, st.x);
-        copy_mat<N, N, R>(ex.C, st.P);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          s_pre[i] = st.x[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) s_pre[N + i * N + j] = st.P[i][j];
-        }
-        fapply<N, P>(st.x, st.P, tot);
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = st.x[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = st.P[i][j];
-        }
+        St<N, R> st;
+        pp.anchor(ex, st);
+        st_store(s_pre, st);
+        pp.apply(st, tot);
+        st_store(a.pre + (base + t) * PS, st);
         lb_store_flag(a.flags + base + t, LB_PREFIX);
       }
     }
   }
   __syncthreads();
 
-  // 4. apply prefixes and write x_{k|k}, P_{k|k}
-  State<N, R> st;
-  bool have;
-  if (t > 0) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      st.x[i] = s_pre[i];
-#pragma unroll
-      for (int j = 0; j < N; ++j) st.P[i][j] = s_pre[N + i * N + j];
-    }
-    if (tid > 0) fapply<N, P>(st.x, st.P, tex);
-    have = true;
-  } else {
-    // tile 0: a thread's in-tile exclusive prefix contains step 1 (A = 0)
-    copy_vec<N, R>(tex.b, st.x);
-    copy_mat<N, N, R>(tex.C, st.P);
-    have = tid > 0;
-  }
-  R* __restrict__ mo = a.m_out + seq * a.T * N;
-  R* __restrict__ Po = a.P_out + seq * a.T * N * N;
+  // 4. this thread's exclusive anchored state: the tile's, then the totals
+  //    of the earlier wavefronts, then the earlier lanes of this wavefront
+  St<N, R> st;
+  if (t > 0) st_load(st, s_pre); else pp.initial(st);
 #pragma unroll 1
-  for (int i = 0; i < L; ++i) {
-    const long k = k0 + i;
-    if (k >= a.T) break;
-    E el = filter_element<N, M, R>(cst, k, yv[i]);
-    if (have) {
-      fapply<N, P>(st.x, st.P, el);
-    } else {
-      copy_vec<N, R>(el.b, st.x);
-      copy_mat<N, N, R>(el.C, st.P);
-      have = true;
-    }
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      mo[k * N + r] = st.x[r];
-#pragma unroll
-      for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.P[r][c];
-    }
-  }
+  for (int w = 0; w < wid; ++w) pp.apply(st, s_wt[w]);
+  if (lane > 0) pp.apply(st, s_x[tid - 1]);
+  const bool have = (t > 0) || (tid > 0);
+  pp.steps(st, have);
   finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
 }
 
-// ===========================================================================
+// ---------------------------------------------------------------------------
+// Forward filter (Algorithm 5): elements (eqs. pkf_init1..3), Lemma 1,
+// anchored state (x_{k|k}, P_{k|k}) = (b, C) of a prefix that holds step 1.
+// ---------------------------------------------------------------------------
+template <int N, int M, class P, int L> struct FilterPipe {
+  using R = typename P::R;
+  using E = FElem<N, R>;
+  const ScanArgs<R>& a;
+  long T, k0;
+  const R* __restrict__ y;
+  R* __restrict__ mo;
+  R* __restrict__ Po;
+  KF_DEV explicit FilterPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV void bind(long seq, long t, int tid) {
+    T = a.T;
+    k0 = t * (long)(L * blockDim.x) + (long)tid * L;
+    y = a.y + seq * T * M;
+    mo = a.m_out + seq * T * N;
+    Po = a.P_out + seq * T * N * N;
+  }
+  KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
+  KF_DEV void load_y(long k, R (&yk)[M]) const {
+#pragma unroll
+    for (int c = 0; c < M; ++c) yk[c] = (k < T) ? y[k * M + c] : R(0);
+  }
+  // Steps are walked with the next step's measurement already in flight.
+  KF_DEV E fold() const {
+    E agg;
+    set_identity(agg);
+    R yn[M];
+    load_y(k0, yn);
+#pragma unroll 1
+    for (int i = 0; i < L; ++i) {
+      const long k = k0 + i;
+      if (k >= T) break;
+      R yk[M];
+      copy_vec<M, R>(yn, yk);
+      load_y(k + 1, yn);
+      E el = filter_element<N, M, R>(a.cst, k, yk);
+      agg = (i == 0) ? el : fcombine<N, P>(agg, el);
+    }
+    return agg;
+  }
+  KF_DEV void apply(St<N, R>& st, const E& e) const { fapply<N, P>(st.v, st.m, e); }
+  KF_DEV void initial(St<N, R>& st) const { st_zero(st); }
+  KF_DEV void anchor(const E& e, St<N, R>& st) const {
+    copy_vec<N, R>(e.b, st.v);
+    copy_mat<N, N, R>(e.C, st.m);
+  }
+  KF_DEV void expand(const St<N, R>& st, E& v) const {
+    set_identity(v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v.A[i][i] = R(0);
+      v.b[i] = st.v[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) v.C[i][j] = st.m[i][j];
+    }
+  }
+  KF_DEV void steps(St<N, R>& st, bool) const {
+    R yn[M];
+    load_y(k0, yn);
+#pragma unroll 1
+    for (int i = 0; i < L; ++i) {
+      const long k = k0 + i;
+      if (k >= T) break;
+      R yk[M];
+      copy_vec<M, R>(yn, yk);
+      load_y(k + 1, yn);
+      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(a.cst, k, yk));
+      st_store_out(k, st);
+    }
+  }
+  KF_DEV void st_store_out(long k, const St<N, R>& st) const {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      mo[k * N + r] = st.v[r];
+#pragma unroll
+      for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.m[r][c];
+    }
+  }
+};
+
+template <int N, int M, class P, int BLOCK, int L>
+__global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
+  FilterPipe<N, M, P, L> pp(a);
+  scan_tile<FilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+}
+
+// ---------------------------------------------------------------------------
+// Time-invariant forward filter (Algorithm 5 for a model with constant F, Q,
+// H, R).  The prior is taken as the anchored state before step 1, so every
+// step carries the generic element of eq. pkf_init1 (the element of eq.
+// pkf_init2 equals (0, m0, P0) (x) that generic element).  By Lemma 1 the
+// matrix part of an aggregate of L consecutive generic elements is the same
+// for every thread (SL) and its vector part is linear in the measurements,
+// so a thread's fold is  b = sum_i PHI[i] y_i, eta = sum_i PSI[i] y_i.  Steps
+// past T are padded with y = 0; the filter is causal, so the outputs at
+// valid steps are unaffected and the padded ones are not written.  The
+// per-step apply is the Kalman predict/update (kf_step).
+// ---------------------------------------------------------------------------
+template <int N, int M, class P, int L> struct FilterTiPipe {
+  using R = typename P::R;
+  using E = FElem<N, R>;
+  using LY = CL<N, M, L>;
+  const ScanArgs<R>& a;
+  long T, k0;
+  R* __restrict__ mo;
+  R* __restrict__ Po;
+  R yv[L][M];
+  KF_DEV explicit FilterTiPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV void bind(long seq, long t, int tid) {
+    T = a.T;
+    k0 = t * (long)(L * blockDim.x) + (long)tid * L;
+    const R* __restrict__ y = a.y + seq * T * M;
+    mo = a.m_out + seq * T * N;
+    Po = a.P_out + seq * T * N * N;
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+      for (int c = 0; c < M; ++c) yv[i][c] = (k0 + i < T) ? y[(k0 + i) * M + c] : R(0);
+  }
+  KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
+  KF_DEV E fold() const {
+    const R* __restrict__ c = a.cst;
+    E e;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R b = R(0), h = R(0);
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          b += c[LY::PHI + i * N * M + r * M + q] * yv[i][q];
+          h += c[LY::PSI + i * N * M + r * M + q] * yv[i][q];
+        }
+      e.b[r] = b;
+      e.e[r] = h;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        e.A[r][j] = c[LY::SL + r * N + j];
+        e.C[r][j] = c[LY::SL + N * N + r * N + j];
+        e.J[r][j] = c[LY::SL + 2 * N * N + r * N + j];
+      }
+    }
+    return e;
+  }
+  KF_DEV void apply(St<N, R>& st, const E& e) const { fapply<N, P>(st.v, st.m, e); }
+  KF_DEV void initial(St<N, R>& st) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      st.v[i] = a.cst[LY::m0 + i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) st.m[i][j] = a.cst[LY::P0 + i * N + j];
+    }
+  }
+  KF_DEV void anchor(const E& e, St<N, R>& st) const {
+    copy_vec<N, R>(e.b, st.v);
+    copy_mat<N, N, R>(e.C, st.m);
+  }
+  KF_DEV void expand(const St<N, R>& st, E& v) const {
+    set_identity(v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v.A[i][i] = R(0);
+      v.b[i] = st.v[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) v.C[i][j] = st.m[i][j];
+    }
+  }
+  KF_DEV void steps(St<N, R>& st, bool) const {
+    R F[N][N], Q[N][N], H[M][N], Rm[M][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        F[i][j] = a.cst[LY::F + i * N + j];
+        Q[i][j] = a.cst[LY::Q + i * N + j];
+      }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) H[i][j] = a.cst[LY::H + i * N + j];
+#pragma unroll
+      for (int j = 0; j < M; ++j) Rm[i][j] = a.cst[LY::Rm + i * M + j];
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const long k = k0 + i;
+      if (k < T) {
+        kf_step<N, M, P>(st.v, st.m, F, Q, H, Rm, yv[i]);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          mo[k * N + r] = st.v[r];
+#pragma unroll
+          for (int cc = 0; cc < N; ++cc) Po[k * N * N + r * N + cc] = st.m[r][cc];
+        }
+      }
+    }
+  }
+};
+
+template <int N, int M, class P, int BLOCK, int L>
+__global__ __launch_bounds__(BLOCK) void k_filter_ti(ScanArgs<typename P::R> a) {
+  FilterTiPipe<N, M, P, L> pp(a);
+  scan_tile<FilterTiPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+}
+
+// ---------------------------------------------------------------------------
 // RTS smoother reverse scan (Algorithm 6).  Scan order is descending time:
 // tile t (scan order) covers time tile ntiles-1-t, thread tid covers time
-// chunk BLOCK-1-tid of it and walks its steps from last to first.
-// ===========================================================================
+// chunk BLOCK-1-tid of it and walks its steps from last to first.  Anchored
+// state (x_{k|T}, P_{k|T}) = (g, L) of a suffix that holds step T.
+// ---------------------------------------------------------------------------
 template <int N, class R> KF_DEV void load_state(const R* __restrict__ m, const R* __restrict__ Pm,
                                                   long k, R (&x)[N], R (&P)[N][N]) {
 #pragma unroll
@@ -397,42 +667,34 @@ template <int N, class R> KF_DEV void load_state(const R* __restrict__ m, const 
   }
 }
 
-template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
+template <int N, int M, class P, int L> struct RtsPipe {
   using R = typename P::R;
   using E = SElem<N, R>;
   using LY = CL<N, M>;
-  constexpr int NW = BLOCK / WAVE;
-  constexpr int TILE = BLOCK * L;
-  constexpr int PS = N + N * N;  // anchored suffix payload: (g, L)
-  __shared__ E s_wt[NW];
-  __shared__ R s_pre[PS];
-  __shared__ long s_tile;
-  __shared__ int s_last;
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-  if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
-  __syncthreads();
-  const long gt = s_tile;
-  const long seq = gt / a.ntiles, t = gt - seq * a.ntiles;  // t: scan order
-  const long tt = a.ntiles - 1 - t;                           // time tile
-  const long k0 = tt * TILE + (long)(BLOCK - 1 - tid) * L;    // first step (time order)
-  const R* __restrict__ mf = a.m_in + seq * a.T * N;
-  const R* __restrict__ Pf = a.P_in + seq * a.T * N * N;
-  R Fm[N][N], Qm[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      Fm[i][j] = a.cst[LY::F + i * N + j];
-      Qm[i][j] = a.cst[LY::Q + i * N + j];
-    }
-  // scan-order operator: p precedes q in scan order, so p is later in time
-  auto op = [](const E& p, const E& q) { return scombine<N, P>(q, p); };
-  auto element = [&](long k) {
-    R x[N], Pk[N][N];
-    load_state<N, R>(mf, Pf, k, x, Pk);
+  const ScanArgs<R>& a;
+  long T, k0;
+  const R* __restrict__ mf;
+  const R* __restrict__ Pf;
+  R* __restrict__ mo;
+  R* __restrict__ Po;
+  KF_DEV explicit RtsPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV void bind(long seq, long t, int tid) {
+    T = a.T;
+    const long tt = a.ntiles - 1 - t;
+    k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
+    mf = a.m_in + seq * T * N;
+    Pf = a.P_in + seq * T * N * N;
+    mo = a.m_out + seq * T * N;
+    Po = a.P_out + seq * T * N * N;
+  }
+  // p precedes q in scan order, so p is the later one in time
+  KF_DEV E op(const E& p, const E& q) const { return scombine<N, P>(q, p); }
+  KF_DEV void load(long k, R (&x)[N], R (&Pk)[N][N]) const {
+    if (k >= 0 && k < T) load_state<N, R>(mf, Pf, k, x, Pk);
+  }
+  KF_DEV E element(long k, const R (&x)[N], const R (&Pk)[N][N]) const {
     E e;
-    if (k == a.T - 1) {  // eq. prts_init2
+    if (k == T - 1) {  // eq. prts_init2
       set_identity(e);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -442,320 +704,187 @@ __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
         for (int j = 0; j < N; ++j) e.L[i][j] = Pk[i][j];
       }
     } else {
+      R Fm[N][N], Qm[N][N];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          Fm[i][j] = a.cst[LY::F + i * N + j];
+          Qm[i][j] = a.cst[LY::Q + i * N + j];
+        }
       e = smooth_element<N, P>(x, Pk, Fm, Qm);
     }
     return e;
-  };
-
-  // 1. thread fold over the chunk, last step first
-  E agg;
-  bool any = false;
-#pragma unroll 1
-  for (int i = L - 1; i >= 0; --i) {
-    const long k = k0 + i;
-    if (k >= a.T) continue;
-    E el = element(k);
-    agg = any ? scombine<N, P>(el, agg) : el;
-    any = true;
   }
-  if (!any) set_identity(agg);
-
-  // 2. workgroup scan (scan order = thread order)
-  E x = agg;
-  wave_inclusive_scan(x, lane, op);
-  if (lane == WAVE - 1) s_wt[wid] = x;
-  E lex = shfl_up(x, 1);
-  __syncthreads();
-  E tex;
-  if (wid > 0) {
-    E wex = s_wt[0];
+  // Steps are walked last to first with the next (earlier) step's filter
+  // moments already in flight.
+  KF_DEV E fold() const {
+    E agg;
+    set_identity(agg);
+    R xn[N], Pn[N][N];
+    load(k0 + L - 1, xn, Pn);
 #pragma unroll 1
-    for (int w = 1; w < wid; ++w) wex = op(wex, s_wt[w]);
-    tex = (lane > 0) ? op(wex, lex) : wex;
-  } else {
-    tex = lex;
-  }
-
-  // 3. publish + look-back
-  const long base = seq * a.ntiles;
-  if (wid == 0) {
-    E tot = s_wt[0];
-#pragma unroll 1
-    for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
-    if (t == 0) {
-      // the time-last tile holds step T (E_T = 0): its aggregate is anchored
-      if (lane == 0) {
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = tot.g[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = tot.L[i][j];
-        }
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
-    } else {
-      if (lane == 0) {
-        gstore(a.agg + (base + t) * E::SIZE, tot);
-        lb_store_flag(a.flags + base + t, LB_AGG);
-      }
-      auto load_agg = [&](long idx, E& v) { gload(v, a.agg + (base + idx) * E::SIZE); };
-      auto expand = [&](long idx, E& v) {
-        const R* p = a.pre + (base + idx) * PS;
-        set_identity(v);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          v.E[i][i] = R(0);
-          v.g[i] = p[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) v.L[i][j] = p[N + i * N + j];
-        }
-      };
-      E ex = lookback<E>(a.flags + base, a.ctr + 2, t, lane, op, load_agg, expand);
-      if (lane == 0) {
-        State<N, R> st;
-        copy_vec<N, R>(ex.g, st.x);
-        copy_mat<N, N, R>(ex.L, st.P);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          s_pre[i] = st.x[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) s_pre[N + i * N + j] = st.P[i][j];
-        }
-        sapply<N, P>(tot, st.x, st.P);
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = st.x[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = st.P[i][j];
-        }
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
+    for (int i = L - 1; i >= 0; --i) {
+      const long k = k0 + i;
+      R x[N], Pk[N][N];
+      copy_vec<N, R>(xn, x);
+      copy_mat<N, N, R>(Pn, Pk);
+      load(k - 1, xn, Pn);
+      if (k < T) agg = scombine<N, P>(element(k, x, Pk), agg);
     }
+    return agg;
   }
-  __syncthreads();
-
-  // 4. apply suffixes, last step first, and write x_{k|T}, P_{k|T}
-  State<N, R> st;
-  bool have;
-  if (t > 0) {
+  KF_DEV void apply(St<N, R>& st, const E& e) const { sapply<N, P>(e, st.v, st.m); }
+  KF_DEV void initial(St<N, R>& st) const { st_zero(st); }
+  KF_DEV void anchor(const E& e, St<N, R>& st) const {
+    copy_vec<N, R>(e.g, st.v);
+    copy_mat<N, N, R>(e.L, st.m);
+  }
+  KF_DEV void expand(const St<N, R>& st, E& v) const {
+    set_identity(v);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      st.x[i] = s_pre[i];
+      v.E[i][i] = R(0);
+      v.g[i] = st.v[i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) st.P[i][j] = s_pre[N + i * N + j];
+      for (int j = 0; j < N; ++j) v.L[i][j] = st.m[i][j];
     }
-    if (tid > 0) sapply<N, P>(tex, st.x, st.P);
-    have = true;
-  } else {
-    copy_vec<N, R>(tex.g, st.x);
-    copy_mat<N, N, R>(tex.L, st.P);
-    have = tid > 0;
   }
-  R* __restrict__ mo = a.m_out + seq * a.T * N;
-  R* __restrict__ Po = a.P_out + seq * a.T * N * N;
+  KF_DEV void steps(St<N, R>& st, bool) const {
+    R xn[N], Pn[N][N];
+    load(k0 + L - 1, xn, Pn);
 #pragma unroll 1
-  for (int i = L - 1; i >= 0; --i) {
-    const long k = k0 + i;
-    if (k >= a.T) continue;
-    if (have) {
-      E el = element(k);
-      sapply<N, P>(el, st.x, st.P);
-    } else {
-      load_state<N, R>(mf, Pf, k, st.x, st.P);  // step T: x_{T|T}, P_{T|T}
-      have = true;
-    }
+    for (int i = L - 1; i >= 0; --i) {
+      const long k = k0 + i;
+      R x[N], Pk[N][N];
+      copy_vec<N, R>(xn, x);
+      copy_mat<N, N, R>(Pn, Pk);
+      load(k - 1, xn, Pn);
+      if (k >= T) continue;
+      sapply<N, P>(element(k, x, Pk), st.v, st.m);
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      mo[k * N + r] = st.x[r];
+      for (int r = 0; r < N; ++r) {
+        mo[k * N + r] = st.v[r];
 #pragma unroll
-      for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.P[r][c];
+        for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.m[r][c];
+      }
     }
   }
-  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
+};
+
+template <int N, int M, class P, int BLOCK, int L>
+__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
+  RtsPipe<N, M, P, L> pp(a);
+  scan_tile<RtsPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
-// ===========================================================================
+// ---------------------------------------------------------------------------
 // Two-filter smoother backward pass (Algorithm 7): reverse scan over
 // (a_2, ..., a_T, e) with the filtering operator; position k (0-based row)
 // holds a_{k+2} for k < T-1 and the identity e at k = T-1, so the suffix at
 // row k is a_{k+2} (x) ... (x) a_T (x) e, whose (eta, J) is eta_{k+1|k+2:T},
-// J_{k+1|k+2:T}.  The combination with the filter result (m_in, P_in) is
-// fused into the apply phase.
-// ===========================================================================
-template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a) {
+// J_{k+1|k+2:T}.  The anchored state is that (eta, J); the combination with
+// the filter result (m_in, P_in) is fused into the step phase.
+// ---------------------------------------------------------------------------
+template <int N, int M, class P, int L> struct TwoFilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
-  constexpr int NW = BLOCK / WAVE;
-  constexpr int TILE = BLOCK * L;
-  constexpr int PS = N + N * N;  // anchored suffix payload: (eta, J)
-  __shared__ E s_wt[NW];
-  __shared__ R s_pre[PS];
-  __shared__ long s_tile;
-  __shared__ int s_last;
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-  if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
-  __syncthreads();
-  const long gt = s_tile;
-  const long seq = gt / a.ntiles, t = gt - seq * a.ntiles;
-  const long tt = a.ntiles - 1 - t;
-  const long k0 = tt * TILE + (long)(BLOCK - 1 - tid) * L;
-  const R* __restrict__ y = a.y + seq * a.T * M;
-  const R* __restrict__ cst = a.cst;
-  auto op = [](const E& p, const E& q) { return fcombine<N, P>(q, p); };
+  const ScanArgs<R>& a;
+  long T, k0;
+  const R* __restrict__ y;
+  const R* __restrict__ mf;
+  const R* __restrict__ Pf;
+  R* __restrict__ mo;
+  R* __restrict__ Po;
+  KF_DEV explicit TwoFilterPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV void bind(long seq, long t, int tid) {
+    T = a.T;
+    const long tt = a.ntiles - 1 - t;
+    k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
+    y = a.y + seq * T * M;
+    mf = a.m_in + seq * T * N;
+    Pf = a.P_in + seq * T * N * N;
+    mo = a.m_out + seq * T * N;
+    Po = a.P_out + seq * T * N * N;
+  }
+  KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(q, p); }
   // measurement of the element at row k: y_{k+2} (row k+1); none at k = T-1
-  R yv[L][M];
+  KF_DEV void load_y(long k, R (&yk)[M]) const {
 #pragma unroll
-  for (int i = 0; i < L; ++i)
-#pragma unroll
-    for (int c = 0; c < M; ++c) yv[i][c] = (k0 + i + 1 < a.T) ? y[(k0 + i + 1) * M + c] : R(0);
-  auto element = [&](long k, const R (&yk)[M]) {
+    for (int c = 0; c < M; ++c) yk[c] = (k >= 0 && k + 1 < T) ? y[(k + 1) * M + c] : R(0);
+  }
+  KF_DEV E element(long k, const R (&yk)[M]) const {
     E e;
-    if (k == a.T - 1) set_identity(e);
-    else e = filter_element<N, M, R>(cst, k + 1, yk);
+    if (k == T - 1) set_identity(e);
+    else e = filter_element<N, M, R>(a.cst, k + 1, yk);
     return e;
-  };
-
-  // 1. thread fold, last step first
-  E agg;
-  bool any = false;
-#pragma unroll
-  for (int i = L - 1; i >= 0; --i) {
-    const long k = k0 + i;
-    if (k >= a.T) continue;
-    E el = element(k, yv[i]);
-    agg = any ? fcombine<N, P>(el, agg) : el;
-    any = true;
   }
-  if (!any) set_identity(agg);
-
-  // 2. workgroup scan
-  E x = agg;
-  wave_inclusive_scan(x, lane, op);
-  if (lane == WAVE - 1) s_wt[wid] = x;
-  E lex = shfl_up(x, 1);
-  __syncthreads();
-  E tex;
-  if (wid > 0) {
-    E wex = s_wt[0];
+  KF_DEV E fold() const {
+    E agg;
+    set_identity(agg);
+    R yn[M];
+    load_y(k0 + L - 1, yn);
 #pragma unroll 1
-    for (int w = 1; w < wid; ++w) wex = op(wex, s_wt[w]);
-    tex = (lane > 0) ? op(wex, lex) : wex;
-  } else {
-    tex = lex;
-  }
-
-  // 3. publish + look-back
-  const long base = seq * a.ntiles;
-  if (wid == 0) {
-    E tot = s_wt[0];
-#pragma unroll 1
-    for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
-    if (t == 0) {
-      if (lane == 0) {
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = tot.e[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = tot.J[i][j];
-        }
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
-    } else {
-      if (lane == 0) {
-        gstore(a.agg + (base + t) * E::SIZE, tot);
-        lb_store_flag(a.flags + base + t, LB_AGG);
-      }
-      auto load_agg = [&](long idx, E& v) { gload(v, a.agg + (base + idx) * E::SIZE); };
-      auto expand = [&](long idx, E& v) {
-        // only (eta, J) of an anchored suffix is ever read: it is the right
-        // operand of every combine it takes part in
-        const R* p = a.pre + (base + idx) * PS;
-        set_identity(v);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          v.e[i] = p[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) v.J[i][j] = p[N + i * N + j];
-        }
-      };
-      E ex = lookback<E>(a.flags + base, a.ctr + 2, t, lane, op, load_agg, expand);
-      if (lane == 0) {
-        R eta[N], J[N][N];
-        copy_vec<N, R>(ex.e, eta);
-        copy_mat<N, N, R>(ex.J, J);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          s_pre[i] = eta[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) s_pre[N + i * N + j] = J[i][j];
-        }
-        fapply_back<N, P>(tot, eta, J);
-        R* p = a.pre + (base + t) * PS;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          p[i] = eta[i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) p[N + i * N + j] = J[i][j];
-        }
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
+    for (int i = L - 1; i >= 0; --i) {
+      const long k = k0 + i;
+      R yk[M];
+      copy_vec<M, R>(yn, yk);
+      load_y(k - 1, yn);
+      if (k < T) agg = fcombine<N, P>(element(k, yk), agg);
     }
+    return agg;
   }
-  __syncthreads();
-
-  // 4. apply suffixes, combine with the filter result, write x_{k|T}, P_{k|T}
-  R eta[N], J[N][N];
-  bool have;
-  if (t > 0) {
+  KF_DEV void apply(St<N, R>& st, const E& e) const { fapply_back<N, P>(e, st.v, st.m); }
+  KF_DEV void initial(St<N, R>& st) const { st_zero(st); }
+  KF_DEV void anchor(const E& e, St<N, R>& st) const {
+    copy_vec<N, R>(e.e, st.v);
+    copy_mat<N, N, R>(e.J, st.m);
+  }
+  // only (eta, J) of an anchored suffix is ever read: it is the right operand
+  // of every combine it takes part in
+  KF_DEV void expand(const St<N, R>& st, E& v) const {
+    set_identity(v);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      eta[i] = s_pre[i];
+      v.e[i] = st.v[i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) J[i][j] = s_pre[N + i * N + j];
+      for (int j = 0; j < N; ++j) v.J[i][j] = st.m[i][j];
     }
-    if (tid > 0) fapply_back<N, P>(tex, eta, J);
-    have = true;
-  } else {
-    copy_vec<N, R>(tex.e, eta);
-    copy_mat<N, N, R>(tex.J, J);
-    have = tid > 0;
   }
-  const R* __restrict__ mf = a.m_in + seq * a.T * N;
-  const R* __restrict__ Pf = a.P_in + seq * a.T * N * N;
-  R* __restrict__ mo = a.m_out + seq * a.T * N;
-  R* __restrict__ Po = a.P_out + seq * a.T * N * N;
+  KF_DEV void load_f(long k, R (&x)[N], R (&Pk)[N][N]) const {
+    if (k >= 0 && k < T) load_state<N, R>(mf, Pf, k, x, Pk);
+  }
+  KF_DEV void steps(St<N, R>& st, bool) const {
+    R yn[M], xn[N], Pn[N][N];
+    load_y(k0 + L - 1, yn);
+    load_f(k0 + L - 1, xn, Pn);
 #pragma unroll 1
-  for (int i = L - 1; i >= 0; --i) {
-    const long k = k0 + i;
-    if (k >= a.T) continue;
-    if (have) {
-      E el = element(k, yv[i]);
-      fapply_back<N, P>(el, eta, J);
-    } else {
-      // suffix of the last row is e alone: eta = 0, J = 0
+    for (int i = L - 1; i >= 0; --i) {
+      const long k = k0 + i;
+      R yk[M], xf[N], Pk[N][N];
+      copy_vec<M, R>(yn, yk);
+      copy_vec<N, R>(xn, xf);
+      copy_mat<N, N, R>(Pn, Pk);
+      load_y(k - 1, yn);
+      load_f(k - 1, xn, Pn);
+      if (k >= T) continue;
+      fapply_back<N, P>(element(k, yk), st.v, st.m);
+      R xs[N], Ps[N][N];
+      tf_combine<N, P>(xf, Pk, st.v, st.m, xs, Ps);
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        eta[r] = R(0);
+        mo[k * N + r] = xs[r];
 #pragma unroll
-        for (int c = 0; c < N; ++c) J[r][c] = R(0);
+        for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = Ps[r][c];
       }
-      have = true;
-    }
-    R xf[N], Pk[N][N], xs[N], Ps[N][N];
-    load_state<N, R>(mf, Pf, k, xf, Pk);
-    tf_combine<N, P>(xf, Pk, eta, J, xs, Ps);
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      mo[k * N + r] = xs[r];
-#pragma unroll
-      for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = Ps[r][c];
     }
   }
-  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
+};
+
+template <int N, int M, class P, int BLOCK, int L>
+__global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a) {
+  TwoFilterPipe<N, M, P, L> pp(a);
+  scan_tile<TwoFilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 }  // namespace kfs

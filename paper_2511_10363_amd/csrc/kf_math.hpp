@@ -12,6 +12,19 @@ namespace kfs {
 
 template <class T> KF_DEV T kabs(T x) { return x < T(0) ? -x : x; }
 
+// Reciprocal and square root used by the factorisations.  FP32: the
+// hardware v_rcp_f32 / v_sqrt_f32 (about 1 ulp), FP64: v_rcp_f64 refined by
+// two Newton steps (below 1 ulp for normal inputs) and the library sqrt.
+KF_DEV float krcp(float x) { return __builtin_amdgcn_rcpf(x); }
+KF_DEV double krcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+KF_DEV float ksqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+KF_DEV double ksqrt(double x) { return sqrt(x); }
+
 // In-place LU with partial pivoting, P M = L U (unit-lower L below the
 // diagonal, whole rows interchanged).  piv[k] is the row swapped into row k
 // at step k; dinv[k] = 1 / U[k][k].
@@ -39,7 +52,7 @@ KF_DEV void lu_factor(T (&M)[N][N], int (&piv)[N], T (&dinv)[N]) {
         M[r][c] = s ? a : b;
       }
     }
-    T inv = T(1) / M[k][k];
+    T inv = krcp(M[k][k]);
     dinv[k] = inv;
 #pragma unroll
     for (int r = k + 1; r < N; ++r) {
@@ -93,8 +106,8 @@ KF_DEV void chol_factor(T (&S)[N][N], T (&dinv)[N]) {
     T d = S[j][j];
 #pragma unroll
     for (int t = 0; t < j; ++t) d -= S[j][t] * S[j][t];
-    T l = sqrt(d);
-    T inv = T(1) / l;
+    T l = ksqrt(d);
+    T inv = krcp(l);
     S[j][j] = l;
     dinv[j] = inv;
 #pragma unroll

@@ -351,3 +351,150 @@ KF_DEV void tf_combine(const typename P::R (&x)[N], const typename P::R (&Pm)[N]
 }
 
 }  // namespace kfs
+
+namespace kfs {
+
+// ---------------------------------------------------------------------------
+// Matrix part (A, C, J) of a filtering element.  Lemma 1 closes over it:
+// A_ij, C_ij, J_ij depend only on the matrix parts of the operands, so for a
+// time-invariant model the matrix part of an aggregate of j consecutive
+// generic elements depends on j alone.
+// ---------------------------------------------------------------------------
+template <int N, class T> struct MPart {
+  T A[N][N];
+  T C[N][N];
+  T J[N][N];
+};
+
+// Coefficients of the vector part of Lemma 1 for left x (matrix part Sx) and
+// right y (matrix part Sy): with M = I + C_x J_y and Z = M^{-1} A_x,
+//   b = P1 b_x + P2 eta_y + b_y,   eta = P3 eta_y - P4 b_x + eta_x,
+//   P1 = A_y M^{-1}, P2 = P1 C_x, P3 = Z^T, P4 = Z^T J_y.
+// Also returns the matrix part of x (x) y.
+template <int N, class T>
+KF_DEV void mpart_combine(const MPart<N, T>& x, const MPart<N, T>& y, MPart<N, T>& o,
+                          T (&P1)[N][N], T (&P2)[N][N], T (&P3)[N][N], T (&P4)[N][N]) {
+  T M[N][N];
+  mm<N, N, N, T>(x.C, y.J, M);
+#pragma unroll
+  for (int i = 0; i < N; ++i) M[i][i] += T(1);
+  int piv[N];
+  T dinv[N];
+  lu_factor<N, T>(M, piv, dinv);
+  // Z = M^{-1} A_x, Y = M^{-1} C_x, and M^{-T} A_y^T = P1^T
+  T B[N][2 * N];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      B[r][c] = x.A[r][c];
+      B[r][N + c] = x.C[r][c];
+    }
+  // P1 = A_y M^{-1}  <=>  P1^T = M^{-T} A_y^T: solve with the transposed
+  // factorisation (U^T then L^T, then undo the row interchanges)
+  T Pt[N][N];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) Pt[r][c] = y.A[c][r];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int t = 0; t < i; ++t)
+#pragma unroll
+      for (int c = 0; c < N; ++c) Pt[i][c] -= M[t][i] * Pt[t][c];
+#pragma unroll
+    for (int c = 0; c < N; ++c) Pt[i][c] *= dinv[i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i)
+#pragma unroll
+    for (int t = i + 1; t < N; ++t)
+#pragma unroll
+      for (int c = 0; c < N; ++c) Pt[i][c] -= M[t][i] * Pt[t][c];
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k)
+#pragma unroll
+    for (int r = k + 1; r < N; ++r) {
+      bool s = (piv[k] == r);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T a = Pt[k][c], b = Pt[r][c];
+        Pt[k][c] = s ? b : a;
+        Pt[r][c] = s ? a : b;
+      }
+    }
+  lu_solve<N, 2 * N, T>(M, piv, dinv, B);
+  T Z[N][N], Y[N][N];
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      Z[r][c] = B[r][c];
+      Y[r][c] = B[r][N + c];
+      P1[r][c] = Pt[c][r];
+      P3[c][r] = B[r][c];  // Z^T
+    }
+  mm<N, N, N, T>(P1, x.C, P2);
+  mm<N, N, N, T>(P3, y.J, P4);
+  mm<N, N, N, T>(y.A, Z, o.A);
+  T AY[N][N];
+  mm<N, N, N, T>(y.A, Y, AY);
+  sym_xyt_plus<N, N, T>(AY, y.A, y.C, o.C);
+  T JA[N][N];
+  mm<N, N, N, T>(y.J, x.A, JA);
+  sym_xty_plus<N, N, T>(Z, JA, x.J, o.J);
+}
+
+// One Kalman predict/update step (Sec. III-A) applied to an anchored state
+// (x, P).  By Lemma 1 with a left operand whose A is zero, (0, x, P) (x) a_k for
+// the generic element a_k of eq. pkf_init1 is exactly this step, so the
+// per-step apply uses it.  S = H P^- H^T + R is factorised (Cholesky) in
+// precision P::S; P = P^- - (H P^-)^T S^{-1} (H P^-) is formed symmetric.
+template <int N, int M, class P, class TF>
+KF_DEV void kf_step(typename P::R (&x)[N], typename P::R (&Pm)[N][N], const TF (&F)[N][N],
+                    const TF (&Q)[N][N], const TF (&H)[M][N], const TF (&Rm)[M][M],
+                    const typename P::R (&y)[M]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  R xp[N], FP[N][N], Pp[N][N];
+  mv<N, N, R>(F, x, xp);
+  mm<N, N, N, R>(F, Pm, FP);
+  sym_xyt_plus<N, N, R>(FP, F, Q, Pp);
+  R HP[M][N];
+  mm<M, N, N, R>(H, Pp, HP);
+  S Sm[M][M], sd[M];
+  sym_xyt_plus<M, N, S>(HP, H, Rm, Sm);
+  chol_factor<M, S>(Sm, sd);
+  S Kt[M][N + 1];  // [S^{-1} H P^- | S^{-1} (y - H x^-)]
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    S s = S(y[r]);
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      Kt[r][c] = S(HP[r][c]);
+      s -= S(H[r][c]) * S(xp[c]);
+    }
+    Kt[r][N] = s;
+  }
+  chol_solve<M, N + 1, S>(Sm, sd, Kt);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    S s = S(xp[i]);
+#pragma unroll
+    for (int t = 0; t < M; ++t) s += S(HP[t][i]) * Kt[t][N];
+    x[i] = R(s);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      S s = S(Pp[i][j]);
+#pragma unroll
+      for (int t = 0; t < M; ++t) s -= S(HP[t][i]) * Kt[t][j];
+      Pm[i][j] = R(s);
+      Pm[j][i] = R(s);
+    }
+}
+
+}  // namespace kfs

@@ -11,8 +11,14 @@ namespace kfs {
 
 constexpr int kBlock = 256;
 
-// Time steps each thread owns in the look-back kernels.
+// Time steps each thread owns: in the scans over full elements, and in the
+// time-invariant scans whose per-thread fold is a linear map of the
+// measurements (so a thread can own more steps).
 constexpr int items_per_thread(int nx) { return nx <= 2 ? 16 : (nx <= 4 ? 8 : 4); }
+constexpr int items_ti(int nx) { return nx <= 4 ? 16 : 8; }
+constexpr int items_min(int nx) {
+  return items_per_thread(nx) < items_ti(nx) ? items_per_thread(nx) : items_ti(nx);
+}
 
 inline size_t word_bytes(int precision) { return precision == KF_PREC_F64 ? 8 : 4; }
 
@@ -24,24 +30,29 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // every call, so a workspace needs no initialisation and carries no state
 // from one call to the next.
 struct Layout {
-  size_t ctr[2];              // [0] tile ticket, [2] look-back timeout flag
+  size_t ctr[2];              // [0] tile ticket, [1] finished blocks, [2] timeout flag
   size_t flags[2];            // look-back status words, slot 0 forward, slot 1 backward
   size_t ctrl_words;          // 32-bit words of the control region at offset 0
   size_t cst;                 // derived model quantities
   size_t agg[2];              // published tile aggregates
   size_t pre[2];              // published anchored prefixes
-  long ntiles;                // tiles per sequence
+  long max_tiles;             // tiles per sequence at the smallest tile size
   size_t total;
 };
+
+inline long ntiles_for(long T, int items) {
+  const long tile = (long)kBlock * items;
+  return (T + tile - 1) / tile;
+}
 
 inline Layout make_layout(int nx, int ny, int precision, long T, long nseq) {
   const size_t w = word_bytes(precision);
   const long n = nx, m = ny;
-  const long tile = (long)kBlock * items_per_thread(nx);
   Layout L{};
-  L.ntiles = (T + tile - 1) / tile;
-  const size_t nt = (size_t)L.ntiles * (size_t)nseq;
-  const size_t cst_words = 6 * n * n + 3 * n * m + n;  // CL<N, M>::SIZE
+  L.max_tiles = ntiles_for(T, items_min(nx));
+  const size_t nt = (size_t)L.max_tiles * (size_t)nseq;
+  const size_t cst_words =                               // CL<N, M, L>::SIZE
+      10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(nx) * n * m;
   const size_t elem_words = 3 * n * n + 2 * n;           // largest element (filtering)
   const size_t pre_words = n + n * n;
   L.ctr[0] = 0;

@@ -21,12 +21,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(entry, model, y, prec):
+def _run(entry, model, y, prec, scan="auto"):
     k = kfscan()
     dev_model = to_dev(model, prec)
     yd = y_dev(y, prec)
     fn = {"filter": k.filter, "rts": k.smooth_rts, "tf": k.smooth_twofilter}[entry]
-    out = fn(dev_model, yd, precision=prec)
+    out = fn(dev_model, yd, precision=prec, scan=scan)
     torch.cuda.synchronize()
     return [o.double().cpu().numpy() for o in out]
 
@@ -41,10 +41,10 @@ def _reference(entry, model, y, prec):
     return list(oracle.smooth_twofilter(*arrs, yy))
 
 
-def _check(entry, model, y, prec, tol=None):
+def _check(entry, model, y, prec, tol=None, scan="auto"):
     tol = TOL[prec] if tol is None else tol
-    _say(entry, prec, "nx=%d ny=%d T=%d" % (model.nx, model.ny, y.shape[0]))
-    got = _run(entry, model, y, prec)
+    _say(entry, prec, scan, "nx=%d ny=%d T=%d" % (model.nx, model.ny, y.shape[0]))
+    got = _run(entry, model, y, prec, scan)
     ref = _reference(entry, model, y, prec)
     names = ["m_filt", "P_filt", "m_smooth", "P_smooth"]
     errs = {}
@@ -60,30 +60,38 @@ def _check(entry, model, y, prec, tol=None):
     return errs
 
 
+SCAN_KINDS = ["lookback", "lookback_generic"]
+
+
+@pytest.mark.parametrize("scan", SCAN_KINDS)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
-def test_tracking_T1000(entry, prec):
-    """Constant-velocity tracking, T = 1000 (several tiles per thread block row)."""
+def test_tracking_T1000(entry, prec, scan):
+    """Constant-velocity tracking, T = 1000."""
     model, y = W.tracking(1000, seed=1)
-    _check(entry, model, y, prec)
+    _check(entry, model, y, prec, scan=scan)
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 7, 63, 64, 65, 1000, 2047, 2048, 2049, 4097, 6000])
+@pytest.mark.parametrize("scan", SCAN_KINDS)
+@pytest.mark.parametrize("T", [1, 2, 3, 7, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096,
+                               4097, 6000, 8193, 12289])
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
-def test_ragged_lengths_f64(entry, T):
-    """Empty-tail tiles, single steps, tile boundaries (2048 steps per tile at nx=4)."""
+def test_ragged_lengths_f64(entry, T, scan):
+    """Empty-tail tiles, single steps and tile boundaries (2048 steps per tile
+    for the full-element scans, 4096 for the time-invariant one at nx=4)."""
     model, y = W.tracking(T, seed=T)
-    _check(entry, model, y, "f64")
+    _check(entry, model, y, "f64", scan=scan)
 
 
+@pytest.mark.parametrize("scan", SCAN_KINDS)
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 4)])
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
-def test_shapes_stable_models(entry, prec, nx, ny):
+def test_shapes_stable_models(entry, prec, nx, ny, scan):
     rng = np.random.default_rng(100 * nx + ny)
     model = W.random_stable_model(nx, ny, 0.95, 0.1, 0.5, rng)
-    y = W.simulate(model, 5000, rng)
-    _check(entry, model, y, prec)
+    y = W.simulate(model, 9000, rng)
+    _check(entry, model, y, prec, scan=scan)
 
 
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
@@ -114,13 +122,14 @@ def test_workspace_reuse_is_deterministic():
     del b, c
 
 
+@pytest.mark.parametrize("scan", SCAN_KINDS)
 @pytest.mark.parametrize("prec", ["f64", "f32", "mixed"])
-def test_full_size_T_2_20(prec):
+def test_full_size_T_2_20(prec, scan):
     """The benchmark workload: tracking model, T = 2^20, filter + RTS smoother,
     every output compared with the oracle."""
     T = 1 << 20
     model, y = W.tracking(T, seed=20251110)
-    errs = _check("rts", model, y, prec)
+    errs = _check("rts", model, y, prec, scan=scan)
     _say("errors", errs)
 
 
