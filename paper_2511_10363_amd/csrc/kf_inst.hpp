@@ -24,8 +24,6 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
   const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
   auto args = [&](int slot, int items) {
     ScanArgs<R> a{};
-    a.cst = cst;
-    a.y = static_cast<const R*>(p.y);
     a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
     a.agg = reinterpret_cast<R*>(ws + L.agg[slot]);
     a.pre = reinterpret_cast<R*>(ws + L.pre[slot]);
@@ -36,25 +34,28 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
     return a;
   };
   auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
+  const R* y = static_cast<const R*>(p.y);
+  R* mf = static_cast<R*>(p.m_filt);
+  R* Pf = static_cast<R*>(p.P_filt);
+  R* ms = static_cast<R*>(p.m_smooth);
+  R* Ps = static_cast<R*>(p.P_smooth);
   if (stages & ST_FORWARD) {
     ScanArgs<R> fa = args(0, generic ? IT : ITI);
-    fa.m_out = static_cast<R*>(p.m_filt);
-    fa.P_out = static_cast<R*>(p.P_filt);
     if (generic)
-      hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), grid(fa), dim3(B), 0, st, fa);
+      hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), grid(fa), dim3(B), 0, st, fa, cst, y,
+                         (const R*)nullptr, (const R*)nullptr, mf, Pf);
     else
-      hipLaunchKernelGGL((k_filter_ti<N, M, P, B, ITI>), grid(fa), dim3(B), 0, st, fa);
+      hipLaunchKernelGGL((k_filter_ti<N, M, P, B, ITI>), grid(fa), dim3(B), 0, st, fa, cst, y,
+                         (const R*)nullptr, (const R*)nullptr, mf, Pf);
   }
   if (op != OP_FILTER && (stages & ST_BACKWARD)) {
     ScanArgs<R> ba = args(1, IT);
-    ba.m_in = static_cast<const R*>(p.m_filt);
-    ba.P_in = static_cast<const R*>(p.P_filt);
-    ba.m_out = static_cast<R*>(p.m_smooth);
-    ba.P_out = static_cast<R*>(p.P_smooth);
     if (op == OP_RTS)
-      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba);
+      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba, cst, y,
+                         (const R*)mf, (const R*)Pf, ms, Ps);
     else
-      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba);
+      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba, cst, y,
+                         (const R*)mf, (const R*)Pf, ms, Ps);
   }
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }

@@ -250,14 +250,9 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   }
 }
 
-// Kernel arguments shared by the three scans.
+// Look-back state and sizes shared by the scans (array pointers travel as
+// separate kernel parameters, see IO below).
 template <class R> struct ScanArgs {
-  const R* cst;   // CL layout
-  const R* y;     // [nseq][T][M]
-  const R* m_in;  // filter means     (RTS, two-filter)
-  const R* P_in;  // filter covariances
-  R* m_out;
-  R* P_out;
   int* flags;      // [nseq * ntiles]
   R* agg;          // [nseq * ntiles][elem size]
   R* pre;          // [nseq * ntiles][anchored prefix size]
@@ -265,6 +260,19 @@ template <class R> struct ScanArgs {
   long T;
   long ntiles;     // tiles per sequence
   long nseq;
+};
+
+// The kernels take the array pointers as separate __restrict__ parameters
+// (not through ScanArgs): with the no-alias guarantee the compiler keeps
+// the uniform model constants in scalar registers (s_load) even after the
+// look-back's atomics, and may reorder the streaming loads and stores.
+template <class R> struct IO {
+  const R* __restrict__ cst;
+  const R* __restrict__ y;
+  const R* __restrict__ m_in;
+  const R* __restrict__ P_in;
+  R* __restrict__ m_out;
+  R* __restrict__ P_out;
 };
 
 // Element of step k (0-based row k, i.e. time step k+1) from its measurement.
@@ -451,17 +459,18 @@ template <int N, int M, class P, int L> struct FilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
   const ScanArgs<R>& a;
+  const IO<R>& io;
   long T, k0;
   const R* __restrict__ y;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV explicit FilterPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV FilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
   KF_DEV void bind(long seq, long t, int tid) {
     T = a.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
-    y = a.y + seq * T * M;
-    mo = a.m_out + seq * T * N;
-    Po = a.P_out + seq * T * N * N;
+    y = io.y + seq * T * M;
+    mo = io.m_out + seq * T * N;
+    Po = io.P_out + seq * T * N * N;
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
   KF_DEV void load_y(long k, R (&yk)[M]) const {
@@ -481,7 +490,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      E el = filter_element<N, M, R>(a.cst, k, yk);
+      E el = filter_element<N, M, R>(io.cst, k, yk);
       agg = (i == 0) ? el : fcombine<N, P>(agg, el);
     }
     return agg;
@@ -512,7 +521,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(a.cst, k, yk));
+      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(io.cst, k, yk));
       st_store_out(k, st);
     }
   }
@@ -526,9 +535,16 @@ template <int N, int M, class P, int L> struct FilterPipe {
   }
 };
 
+#define KFS_IO_PARAMS(R)                                                                  \
+  const R* __restrict__ cst, const R* __restrict__ y, const R* __restrict__ m_in,        \
+      const R* __restrict__ P_in, R* __restrict__ m_out, R* __restrict__ P_out
+#define KFS_IO_MAKE(R) const IO<R> io{cst, y, m_in, P_in, m_out, P_out}
+
 template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a) {
-  FilterPipe<N, M, P, L> pp(a);
+__global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a,
+                                                  KFS_IO_PARAMS(typename P::R)) {
+  KFS_IO_MAKE(typename P::R);
+  FilterPipe<N, M, P, L> pp(a, io);
   scan_tile<FilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
@@ -549,17 +565,18 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   using E = FElem<N, R>;
   using LY = CL<N, M, L>;
   const ScanArgs<R>& a;
+  const IO<R>& io;
   long T, k0;
   R* __restrict__ mo;
   R* __restrict__ Po;
   R yv[L][M];
-  KF_DEV explicit FilterTiPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV FilterTiPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
   KF_DEV void bind(long seq, long t, int tid) {
     T = a.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
-    const R* __restrict__ y = a.y + seq * T * M;
-    mo = a.m_out + seq * T * N;
-    Po = a.P_out + seq * T * N * N;
+    const R* __restrict__ y = io.y + seq * T * M;
+    mo = io.m_out + seq * T * N;
+    Po = io.P_out + seq * T * N * N;
 #pragma unroll
     for (int i = 0; i < L; ++i)
 #pragma unroll
@@ -567,7 +584,7 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
   KF_DEV E fold() const {
-    const R* __restrict__ c = a.cst;
+    const R* __restrict__ c = io.cst;
     E e;
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -594,9 +611,9 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   KF_DEV void initial(St<N, R>& st) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      st.v[i] = a.cst[LY::m0 + i];
+      st.v[i] = io.cst[LY::m0 + i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) st.m[i][j] = a.cst[LY::P0 + i * N + j];
+      for (int j = 0; j < N; ++j) st.m[i][j] = io.cst[LY::P0 + i * N + j];
     }
   }
   KF_DEV void anchor(const E& e, St<N, R>& st) const {
@@ -619,15 +636,15 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        F[i][j] = a.cst[LY::F + i * N + j];
-        Q[i][j] = a.cst[LY::Q + i * N + j];
+        F[i][j] = io.cst[LY::F + i * N + j];
+        Q[i][j] = io.cst[LY::Q + i * N + j];
       }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) H[i][j] = a.cst[LY::H + i * N + j];
+      for (int j = 0; j < N; ++j) H[i][j] = io.cst[LY::H + i * N + j];
 #pragma unroll
-      for (int j = 0; j < M; ++j) Rm[i][j] = a.cst[LY::Rm + i * M + j];
+      for (int j = 0; j < M; ++j) Rm[i][j] = io.cst[LY::Rm + i * M + j];
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -646,8 +663,10 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
 };
 
 template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_filter_ti(ScanArgs<typename P::R> a) {
-  FilterTiPipe<N, M, P, L> pp(a);
+__global__ __launch_bounds__(BLOCK) void k_filter_ti(ScanArgs<typename P::R> a,
+                                                     KFS_IO_PARAMS(typename P::R)) {
+  KFS_IO_MAKE(typename P::R);
+  FilterTiPipe<N, M, P, L> pp(a, io);
   scan_tile<FilterTiPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
@@ -672,20 +691,21 @@ template <int N, int M, class P, int L> struct RtsPipe {
   using E = SElem<N, R>;
   using LY = CL<N, M>;
   const ScanArgs<R>& a;
+  const IO<R>& io;
   long T, k0;
   const R* __restrict__ mf;
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV explicit RtsPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV RtsPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
   KF_DEV void bind(long seq, long t, int tid) {
     T = a.T;
     const long tt = a.ntiles - 1 - t;
     k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
-    mf = a.m_in + seq * T * N;
-    Pf = a.P_in + seq * T * N * N;
-    mo = a.m_out + seq * T * N;
-    Po = a.P_out + seq * T * N * N;
+    mf = io.m_in + seq * T * N;
+    Pf = io.P_in + seq * T * N * N;
+    mo = io.m_out + seq * T * N;
+    Po = io.P_out + seq * T * N * N;
   }
   // p precedes q in scan order, so p is the later one in time
   KF_DEV E op(const E& p, const E& q) const { return scombine<N, P>(q, p); }
@@ -709,8 +729,8 @@ template <int N, int M, class P, int L> struct RtsPipe {
       for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          Fm[i][j] = a.cst[LY::F + i * N + j];
-          Qm[i][j] = a.cst[LY::Q + i * N + j];
+          Fm[i][j] = io.cst[LY::F + i * N + j];
+          Qm[i][j] = io.cst[LY::Q + i * N + j];
         }
       e = smooth_element<N, P>(x, Pk, Fm, Qm);
     }
@@ -773,8 +793,10 @@ template <int N, int M, class P, int L> struct RtsPipe {
 };
 
 template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a) {
-  RtsPipe<N, M, P, L> pp(a);
+__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a,
+                                               KFS_IO_PARAMS(typename P::R)) {
+  KFS_IO_MAKE(typename P::R);
+  RtsPipe<N, M, P, L> pp(a, io);
   scan_tile<RtsPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
@@ -790,22 +812,23 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
   const ScanArgs<R>& a;
+  const IO<R>& io;
   long T, k0;
   const R* __restrict__ y;
   const R* __restrict__ mf;
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV explicit TwoFilterPipe(const ScanArgs<R>& a_) : a(a_) {}
+  KF_DEV TwoFilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
   KF_DEV void bind(long seq, long t, int tid) {
     T = a.T;
     const long tt = a.ntiles - 1 - t;
     k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
-    y = a.y + seq * T * M;
-    mf = a.m_in + seq * T * N;
-    Pf = a.P_in + seq * T * N * N;
-    mo = a.m_out + seq * T * N;
-    Po = a.P_out + seq * T * N * N;
+    y = io.y + seq * T * M;
+    mf = io.m_in + seq * T * N;
+    Pf = io.P_in + seq * T * N * N;
+    mo = io.m_out + seq * T * N;
+    Po = io.P_out + seq * T * N * N;
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(q, p); }
   // measurement of the element at row k: y_{k+2} (row k+1); none at k = T-1
@@ -816,7 +839,7 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
   KF_DEV E element(long k, const R (&yk)[M]) const {
     E e;
     if (k == T - 1) set_identity(e);
-    else e = filter_element<N, M, R>(a.cst, k + 1, yk);
+    else e = filter_element<N, M, R>(io.cst, k + 1, yk);
     return e;
   }
   KF_DEV E fold() const {
@@ -882,8 +905,10 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
 };
 
 template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a) {
-  TwoFilterPipe<N, M, P, L> pp(a);
+__global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a,
+                                                     KFS_IO_PARAMS(typename P::R)) {
+  KFS_IO_MAKE(typename P::R);
+  TwoFilterPipe<N, M, P, L> pp(a, io);
   scan_tile<TwoFilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
