@@ -64,6 +64,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="f32", choices=["f32", "mixed", "f64"])
     ap.add_argument("--log2T", type=int, default=20)
+    ap.add_argument("--scan", default="lookback",
+                    choices=["lookback", "lookback_generic", "blelloch", "hillis_steele"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
@@ -92,7 +94,7 @@ def main() -> int:
     dt = kfscan.dtype_for(prec)
     dmodel = kfscan.model_to_device(model.arrays(), prec, dev)
     y = torch.as_tensor(y_np).to(dev, dt).contiguous()
-    plan = kfscan.Plan(dmodel, y, precision=prec, smoother=True)
+    plan = kfscan.Plan(dmodel, y, precision=prec, scan=args.scan, smoother=True)
 
     def one_pass(evs=None):
         if evs is not None:
@@ -120,6 +122,21 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
+    # device-copy reference: 256 MiB through the library's plain copy kernel,
+    # timed with events (also the calibration dispatch of the counter runs)
+    nbytes = 256 << 20
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    kfscan.device_copy(dst, src)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(3):
+        kfscan.device_copy(dst, src)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * nbytes * 3 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del src, dst
+
     wall = t1 - t0
     ms_per_step = wall / K * 1e3
     value = T * K / wall
@@ -138,7 +155,7 @@ def main() -> int:
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_bytes = kern[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, "tracking_T2^%d" % args.log2T, prec)
+    traffic = load_traffic(dom, "tracking_T2^%d_%s" % (args.log2T, args.scan), prec)
 
     # accuracy of this run against the FP64 oracle, and the CPU baseline
     m_f, P_f, m_s, P_s = (t[0].double().cpu().numpy() for t in plan.outputs())
@@ -187,7 +204,7 @@ def main() -> int:
         "config": {"workload": "cv_tracking_nx4_ny2_T2^%d" % args.log2T, "T": T, "nx": n, "ny": m,
                    "dt": 0.1, "q": 1.0, "r": 0.25, "sequences": 1,
                    "pipeline": "kf_prepare+kf_pass_filter+kf_pass_rts",
-                   "scan": "lookback", "seed": args.seed},
+                   "scan": args.scan, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom},
         "cpu_baseline": cpu,
@@ -195,6 +212,7 @@ def main() -> int:
         "kernel_ms": {"k_prepare": float(t_prep.mean()), "k_filter": float(t_filt.mean()),
                       "k_rts": float(t_rts.mean())},
         "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
+        "copy_GBps": copy_gbps,
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))

@@ -38,9 +38,10 @@
  *
  * Workspace: device memory of at least kf_workspace_size() bytes, 256-byte
  * aligned, owned by the caller, with no initialisation required: the first
- * kernel of every call zeroes the workspace's control words (tile tickets,
- * look-back status words), so one workspace serves any sequence of calls
- * issued in order on one stream, whatever their shapes and precisions.
+ * kernel of every call zeroes the workspace's control region (tile tickets,
+ * look-back status words and payloads, pass epochs), so one workspace serves
+ * any sequence of calls issued in order on one stream, whatever their shapes
+ * and precisions.
  * Calls that may run concurrently need distinct workspaces.
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
@@ -121,6 +122,12 @@ kf_status kf_workspace_size(const kf_problem *p, size_t *bytes);
  * convenience; workspaces need no clearing). */
 kf_status kf_workspace_clear(void *workspace, size_t bytes, void *stream);
 
+/* Copy `bytes` (a multiple of 16, both pointers 16-byte aligned) from device
+ * memory src to device memory dst with one plain streaming kernel (k_copy16):
+ * it reads and writes exactly `bytes`, which makes it the reference dispatch
+ * for calibrating hardware traffic counters.  Asynchronous on `stream`. */
+kf_status kf_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Diagnostic, synchronises `stream`: sets *timed_out to 1 if a look-back wait
  * in the last call that used this workspace gave up (a predecessor tile
  * never published within about a second, so that call's outputs are
@@ -151,8 +158,9 @@ kf_status kf_smooth_twofilter(const kf_problem *p, void *workspace, size_t works
  *   kf_pass_twofilter the backward scan and combination of Algorithm 7 (reads
  *                     y, m_filt, P_filt, writes m_smooth, P_smooth).
  * A pass needs a kf_prepare of the same problem earlier in stream order on
- * the same workspace; each pass leaves its own control words zeroed, so
- * passes may be repeated after one kf_prepare.
+ * the same workspace; each pass advances an epoch word in the workspace that
+ * tags everything it publishes, so passes may be repeated after one
+ * kf_prepare (up to 2^30 times).
  * kf_filter = kf_prepare + kf_pass_filter;
  * kf_smooth_rts = kf_prepare + kf_pass_filter + kf_pass_rts;
  * kf_smooth_twofilter = kf_prepare + kf_pass_filter + kf_pass_twofilter. */

@@ -16,6 +16,14 @@ __global__ void k_fill_zero(unsigned* __restrict__ p, size_t n) {
     p[i] = 0u;
 }
 
+// Streaming device copy, 16 bytes per lane per iteration, grid-stride.
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 bool shape_built(int nx, int ny) {
 #define KFS_TEST(n, m) \
   if (nx == n && ny == m) return true;
@@ -32,8 +40,9 @@ static kf_status check_sizes(const kf_problem* p) {
   // tile counts and element offsets stay well inside 32-bit grid limits
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   if (!shape_built(p->nx, p->ny)) return KF_ERR_UNSUPPORTED;
-  if (p->scan == KF_SCAN_BLELLOCH || p->scan == KF_SCAN_HILLIS_STEELE) return KF_ERR_UNSUPPORTED;
-  const Layout L = make_layout(p->nx, p->ny, p->precision, p->T, p->nseq);
+  // the tree scans put sequences on the grid's y dimension
+  if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
+  const Layout L = make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
   if ((double)L.max_tiles * (double)p->nseq > 2147483647.0) return KF_ERR_INVALID_ARG;
   return KF_OK;
 }
@@ -48,7 +57,7 @@ static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws
     return KF_ERR_INVALID_ARG;
   if (op != OP_FILTER && (stages & ST_BACKWARD) && (!p->m_smooth || !p->P_smooth))
     return KF_ERR_INVALID_ARG;
-  const Layout L = make_layout(p->nx, p->ny, p->precision, p->T, p->nseq);
+  const Layout L = make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
     return KF_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -86,7 +95,7 @@ kf_status kf_workspace_size(const kf_problem* p, size_t* bytes) {
   if (!bytes) return KF_ERR_INVALID_ARG;
   kf_status s = kfs::check_sizes(p);
   if (s != KF_OK) return s;
-  *bytes = kfs::make_layout(p->nx, p->ny, p->precision, p->T, p->nseq).total;
+  *bytes = kfs::make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq).total;
   return KF_OK;
 }
 
@@ -100,12 +109,24 @@ kf_status kf_workspace_clear(void* workspace, size_t bytes, void* stream) {
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }
 
+kf_status kf_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || (bytes & 15u) != 0 || ((reinterpret_cast<uintptr_t>(dst) |
+                                             reinterpret_cast<uintptr_t>(src)) & 15u) != 0)
+    return KF_ERR_INVALID_ARG;
+  const size_t n = bytes / 16;
+  if (n == 0) return KF_OK;
+  const unsigned grid = (unsigned)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+  hipLaunchKernelGGL(kfs::k_copy16, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+  return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+}
+
 kf_status kf_workspace_timed_out(const kf_problem* p, const void* ws, size_t ws_bytes,
                                  int32_t* timed_out, void* stream) {
   if (!timed_out) return KF_ERR_INVALID_ARG;
   kf_status s = kfs::check_sizes(p);
   if (s != KF_OK) return s;
-  const kfs::Layout L = kfs::make_layout(p->nx, p->ny, p->precision, p->T, p->nseq);
+  const kfs::Layout L = kfs::make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
   if (!ws || ws_bytes < L.total) return KF_ERR_WORKSPACE;
   unsigned words[2] = {0u, 0u};
   hipStream_t st = static_cast<hipStream_t>(stream);

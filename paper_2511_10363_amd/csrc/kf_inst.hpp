@@ -2,6 +2,7 @@
 // per-precision translation units, which list the shapes that are built.
 #pragma once
 #include "kf_kernels.hpp"
+#include "kf_tree.hpp"
 #include "kf_plan.hpp"
 
 namespace kfs {
@@ -21,24 +22,39 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
                        static_cast<const R*>(p.H), static_cast<const R*>(p.R),
                        static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
                        reinterpret_cast<unsigned*>(ws), L.ctrl_words);
-  const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
-  auto args = [&](int slot, int items) {
-    ScanArgs<R> a{};
-    a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
-    a.agg = reinterpret_cast<R*>(ws + L.agg[slot]);
-    a.pre = reinterpret_cast<R*>(ws + L.pre[slot]);
-    a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
-    a.T = p.T;
-    a.ntiles = ntiles_for(p.T, items);
-    a.nseq = p.nseq;
-    return a;
-  };
-  auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
   const R* y = static_cast<const R*>(p.y);
   R* mf = static_cast<R*>(p.m_filt);
   R* Pf = static_cast<R*>(p.P_filt);
   R* ms = static_cast<R*>(p.m_smooth);
   R* Ps = static_cast<R*>(p.P_smooth);
+  if (is_tree_scan(p.scan)) {
+    const bool hs = (p.scan == KF_SCAN_HILLIS_STEELE);
+    R* X0 = reinterpret_cast<R*>(ws + L.tree[0]);
+    R* X1 = reinterpret_cast<R*>(ws + L.tree[1]);
+    TreeIO<R> io{cst, y, mf, Pf, mf, Pf, p.T, L.tree_positions};
+    if (stages & ST_FORWARD) tree_scan<TreeFilter<N, M, P>>(io, hs, p.nseq, X0, X1, st);
+    if (op != OP_FILTER && (stages & ST_BACKWARD)) {
+      io.m_out = ms;
+      io.P_out = Ps;
+      if (op == OP_RTS) tree_scan<TreeRts<N, M, P>>(io, hs, p.nseq, X0, X1, st);
+      else tree_scan<TreeTwoFilter<N, M, P>>(io, hs, p.nseq, X0, X1, st);
+    }
+    return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+  }
+  const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
+  auto args = [&](int slot, int items) {
+    ScanArgs<R> a{};
+    a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
+    a.agg = reinterpret_cast<u64*>(ws + L.agg[slot]);
+    a.pre = reinterpret_cast<u64*>(ws + L.pre[slot]);
+    a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
+    a.T = p.T;
+    a.ntiles = ntiles_for(p.T, items);
+    a.nseq = p.nseq;
+    a.lb_group = lookback_group(a.ntiles);
+    return a;
+  };
+  auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
   if (stages & ST_FORWARD) {
     ScanArgs<R> fa = args(0, generic ? IT : ITI);
     if (generic)

@@ -41,36 +41,44 @@ template <int N, int M, int L = 1> struct CL {
                        PSI = PHI + L * N * M, SIZE = PSI + L * N * M;
 };
 
-// The preparation launch also zeroes the workspace's control words (tile
-// tickets, timeout flags, look-back status words) with a grid-stride loop.
+// The preparation launch also zeroes the workspace's control region (tile
+// tickets, epochs, timeout flags, look-back status words and payloads) with a
+// grid-stride loop.  In block 0, wavefront 0 derives the generic element and
+// the aggregate tables while wavefront 1 derives the first element, so the two
+// serial FP64 chains overlap.
+//
+// Aggregate tables by doubling (L a power of two): with S_h the matrix part of
+// h consecutive generic elements and PHI_h[j], PSI_h[j] (j < h) its vector
+// coefficients, Lemma 1 for S_h (x) S_h (coefficients P1..P4, see
+// mpart_combine) gives
+//   j <  h:  PHI_2h[j] = P1 PHI_h[j],              PSI_2h[j] = PSI_h[j] - P4 PHI_h[j]
+//   j >= h:  PHI_2h[j] = P2 PSI_h[j-h] + PHI_h[j-h], PSI_2h[j] = P3 PSI_h[j-h]
+// starting from S_1 = (A, C, J), PHI_1[0] = K, PSI_1[0] = W.
 template <int N, int M, class R, int L>
 __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const R* __restrict__ Q_,
                                                  const R* __restrict__ H_, const R* __restrict__ R_,
                                                  const R* __restrict__ m0_,
                                                  const R* __restrict__ P0_, R* __restrict__ cst,
                                                  unsigned* __restrict__ ctrl, size_t ctrl_words) {
+  static_assert((L & (L - 1)) == 0 && L <= 64, "aggregate length must be a power of two");
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ctrl_words;
        i += (size_t)gridDim.x * blockDim.x)
     ctrl[i] = 0u;
   if (blockIdx.x != 0) return;
   using D = double;
   using LY = CL<N, M, L>;
-  __shared__ MPart<N, D> sS[L + 1];  // sS[j]: matrix part of j consecutive generic elements
-  __shared__ D sP[L][4][N][N];       // vector coefficients of sS[i] (x) sS[1]
-  __shared__ D sK[N][M], sW[N][M];
+  __shared__ MPart<N, D> sS;          // S_h
+  __shared__ D sPc[4][N][N];          // P1..P4 of S_h (x) S_h
+  __shared__ D sPHI[L][N][M], sPSI[L][N][M];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    D F[N][N], Q[N][N], H[M][N], Rm[M][M], m0[N], P0[N][N];
+  auto load_model = [&](D (&F)[N][N], D (&Q)[N][N], D (&H)[M][N], D (&Rm)[M][M]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      m0[i] = D(m0_[i]);
+    for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         F[i][j] = D(F_[i * N + j]);
         Q[i][j] = D(Q_[i * N + j]);
-        P0[i][j] = D(P0_[i * N + j]);
       }
-    }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
@@ -78,7 +86,11 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
 #pragma unroll
       for (int j = 0; j < M; ++j) Rm[i][j] = D(R_[i * M + j]);
     }
-    // generic element
+  };
+  if (tid == 0) {
+    // generic element (eq. pkf_init1)
+    D F[N][N], Q[N][N], H[M][N], Rm[M][M];
+    load_model(F, Q, H, Rm);
     D HQ[M][N], S[M][M], sd[M];
     mm<M, N, N, D>(H, Q, HQ);
     sym_xyt_plus<M, N, D>(HQ, H, Rm, S);
@@ -103,14 +115,42 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     mm<M, N, N, D>(H, F, HF);
     copy_mat<M, N, D>(HF, Wt);
     chol_solve<M, N, D>(S, sd, Wt);
-    D Jm[N][N];
-    D Z[N][N];
+    D Jm[N][N], Z[N][N];
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) Z[i][j] = D(0);
     sym_xty_plus<N, M, D>(Wt, HF, Z, Jm);  // J = (S^{-1} H F)^T (H F)
-    // first element
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const D Cs = 0.5 * (C[i][j] + C[j][i]);
+        cst[LY::A + i * N + j] = R(A[i][j]);
+        cst[LY::C + i * N + j] = R(Cs);
+        cst[LY::J + i * N + j] = R(Jm[i][j]);
+        sS.A[i][j] = A[i][j];
+        sS.C[i][j] = Cs;
+        sS.J[i][j] = Jm[i][j];
+      }
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        cst[LY::K + i * M + t] = R(Kt[t][i]);
+        cst[LY::W + i * M + t] = R(Wt[t][i]);
+        sPHI[0][i][t] = Kt[t][i];
+        sPSI[0][i][t] = Wt[t][i];
+      }
+    }
+  } else if (tid == WAVE) {
+    // first element (eq. pkf_init2) and the model copies
+    D F[N][N], Q[N][N], H[M][N], Rm[M][M], m0[N], P0[N][N];
+    load_model(F, Q, H, Rm);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      m0[i] = D(m0_[i]);
+#pragma unroll
+      for (int j = 0; j < N; ++j) P0[i][j] = D(P0_[i * N + j]);
+    }
     D x[N], FP[N][N], P[N][N];
     mv<N, N, D>(F, m0, x);
     mm<N, N, N, D>(F, P0, FP);
@@ -122,14 +162,17 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     D K1t[M][N];
     copy_mat<M, N, D>(HP, K1t);
     chol_solve<M, N, D>(S1, s1d, K1t);
-    D Hx[M], c1[N], C1[N][N];
+    D Hx[M];
     mv<M, N, D>(H, x, Hx);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       D s = x[i];
 #pragma unroll
       for (int t = 0; t < M; ++t) s -= K1t[t][i] * Hx[t];
-      c1[i] = s;
+      cst[LY::c1 + i] = R(s);
+      cst[LY::m0 + i] = R(m0[i]);
+#pragma unroll
+      for (int t = 0; t < M; ++t) cst[LY::K1 + i * M + t] = R(K1t[t][i]);
     }
     // C_1 = P - K1 S1 K1^T = P - (H P)^T S1^{-1} (H P)
 #pragma unroll
@@ -139,36 +182,17 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
         D s = P[i][j];
 #pragma unroll
         for (int t = 0; t < M; ++t) s -= HP[t][i] * K1t[t][j];
-        C1[i][j] = s;
-        C1[j][i] = s;
+        cst[LY::C1 + i * N + j] = R(s);
+        cst[LY::C1 + j * N + i] = R(s);
       }
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      cst[LY::c1 + i] = R(c1[i]);
-      cst[LY::m0 + i] = R(m0[i]);
+    for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const D Cs = 0.5 * (C[i][j] + C[j][i]);
-        cst[LY::A + i * N + j] = R(A[i][j]);
-        cst[LY::C + i * N + j] = R(Cs);
-        cst[LY::J + i * N + j] = R(Jm[i][j]);
-        cst[LY::C1 + i * N + j] = R(C1[i][j]);
         cst[LY::F + i * N + j] = R(F[i][j]);
         cst[LY::Q + i * N + j] = R(0.5 * (Q[i][j] + Q[j][i]));
         cst[LY::P0 + i * N + j] = R(0.5 * (P0[i][j] + P0[j][i]));
-        sS[1].A[i][j] = A[i][j];
-        sS[1].C[i][j] = Cs;
-        sS[1].J[i][j] = Jm[i][j];
       }
-#pragma unroll
-      for (int t = 0; t < M; ++t) {
-        cst[LY::K + i * M + t] = R(Kt[t][i]);
-        cst[LY::W + i * M + t] = R(Wt[t][i]);
-        cst[LY::K1 + i * M + t] = R(K1t[t][i]);
-        sK[i][t] = Kt[t][i];
-        sW[i][t] = Wt[t][i];
-      }
-    }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
@@ -178,64 +202,54 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     }
   }
   __syncthreads();
-  // matrix parts of 2..L consecutive generic elements by doubling:
-  // sS[h + i] = sS[h] (x) sS[i] for 1 <= i <= h
+#pragma unroll 1
   for (int h = 1; h < L; h *= 2) {
-    if (tid >= 1 && tid <= h && h + tid <= L) {
+    if (tid == 0) {
       D P1[N][N], P2[N][N], P3[N][N], P4[N][N];
       MPart<N, D> o;
-      mpart_combine<N, D>(sS[h], sS[tid], o, P1, P2, P3, P4);
-      sS[h + tid] = o;
+      mpart_combine<N, D>(sS, sS, o, P1, P2, P3, P4);
+      sS = o;
+      copy_mat<N, N, D>(P1, sPc[0]);
+      copy_mat<N, N, D>(P2, sPc[1]);
+      copy_mat<N, N, D>(P3, sPc[2]);
+      copy_mat<N, N, D>(P4, sPc[3]);
+    }
+    __syncthreads();
+    D nphi[N][M], npsi[N][M];
+    const int j = tid;
+    if (j < 2 * h) {
+      if (j < h) {
+        D T1[N][M];
+        mm<N, N, M, D>(sPc[0], sPHI[j], nphi);
+        mm<N, N, M, D>(sPc[3], sPHI[j], T1);
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+          for (int c = 0; c < M; ++c) npsi[r][c] = sPSI[j][r][c] - T1[r][c];
+      } else {
+        D T1[N][M];
+        mm<N, N, M, D>(sPc[1], sPSI[j - h], T1);
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+          for (int c = 0; c < M; ++c) nphi[r][c] = T1[r][c] + sPHI[j - h][r][c];
+        mm<N, N, M, D>(sPc[2], sPSI[j - h], npsi);
+      }
+    }
+    __syncthreads();
+    if (j < 2 * h) {
+      copy_mat<N, M, D>(nphi, sPHI[j]);
+      copy_mat<N, M, D>(npsi, sPSI[j]);
     }
     __syncthreads();
   }
-  // vector coefficients of sS[i] (x) sS[1], i = 1 .. L-1
-  if (tid >= 1 && tid < L) {
-    D P1[N][N], P2[N][N], P3[N][N], P4[N][N];
-    MPart<N, D> o;
-    mpart_combine<N, D>(sS[tid], sS[1], o, P1, P2, P3, P4);
-    copy_mat<N, N, D>(P1, sP[tid][0]);
-    copy_mat<N, N, D>(P2, sP[tid][1]);
-    copy_mat<N, N, D>(P3, sP[tid][2]);
-    copy_mat<N, N, D>(P4, sP[tid][3]);
-  }
-  __syncthreads();
-  // coefficient of y_j in the L-aggregate: step j enters as (K y_j, W y_j)
-  // when j = 0, else through sS[j] (x) sS[1]; every later step i then maps
-  // eta <- eta - P4(i) b and b <- P1(i) b
   if (tid < L) {
-    const int j = tid;
-    D Bc[N][M], Ec[N][M];
-    if (j == 0) {
-      copy_mat<N, M, D>(sK, Bc);
-      copy_mat<N, M, D>(sW, Ec);
-    } else {
-      D PW[N][M];
-      mm<N, N, M, D>(sP[j][1], sW, PW);
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < M; ++c) Bc[r][c] = PW[r][c] + sK[r][c];
-      mm<N, N, M, D>(sP[j][2], sW, Ec);
-    }
-    for (int i = j + 1; i < L; ++i) {
-      D T1[N][M], T2[N][M];
-      mm<N, N, M, D>(sP[i][3], Bc, T1);
-      mm<N, N, M, D>(sP[i][0], Bc, T2);
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          Ec[r][c] -= T1[r][c];
-          Bc[r][c] = T2[r][c];
-        }
-    }
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        cst[LY::PHI + j * N * M + r * M + c] = R(Bc[r][c]);
-        cst[LY::PSI + j * N * M + r * M + c] = R(Ec[r][c]);
+        cst[LY::PHI + tid * N * M + r * M + c] = R(sPHI[tid][r][c]);
+        cst[LY::PSI + tid * N * M + r * M + c] = R(sPSI[tid][r][c]);
       }
   }
   if (tid == 0) {
@@ -243,23 +257,25 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        cst[LY::SL + i * N + j] = R(sS[L].A[i][j]);
-        cst[LY::SL + N * N + i * N + j] = R(sS[L].C[i][j]);
-        cst[LY::SL + 2 * N * N + i * N + j] = R(sS[L].J[i][j]);
+        cst[LY::SL + i * N + j] = R(sS.A[i][j]);
+        cst[LY::SL + N * N + i * N + j] = R(sS.C[i][j]);
+        cst[LY::SL + 2 * N * N + i * N + j] = R(sS.J[i][j]);
       }
   }
 }
 
 // Look-back state and sizes shared by the scans (array pointers travel as
-// separate kernel parameters, see IO below).
+// separate kernel parameters, see IO below).  agg and pre hold tagged words
+// (kf_scan.hpp): kWords<R> per scalar.
 template <class R> struct ScanArgs {
-  int* flags;      // [nseq * ntiles]
-  R* agg;          // [nseq * ntiles][elem size]
-  R* pre;          // [nseq * ntiles][anchored prefix size]
-  unsigned* ctr;   // [0] tile ticket, [1] finished blocks, [2] look-back timeout flag
+  int* flags;      // [nseq * ntiles] status words
+  u64* agg;        // [nseq * ntiles][elem size * kWords]
+  u64* pre;        // [nseq * ntiles][anchored prefix size * kWords]
+  unsigned* ctr;   // [0] tile ticket, [1] finished blocks, [2] look-back timeout flag, [3] epoch
   long T;
   long ntiles;     // tiles per sequence
   long nseq;
+  int lb_group;    // tiles per lane in a look-back window
 };
 
 // The kernels take the array pointers as separate __restrict__ parameters
@@ -302,25 +318,18 @@ KF_DEV FElem<N, R> filter_element(const R* __restrict__ cst, long k, const R (&y
   return a;
 }
 
-// After the last block of a scan has finished, clear that scan's status
-// words and tile ticket, so the pass can be enqueued again without another
-// preparation launch.  The timeout flag (ctr[2]) is left for diagnosis.
-template <int BLOCK>
-KF_DEV void finish_grid(int* __restrict__ flags, unsigned* __restrict__ ctr, long nflags,
-                        int* s_last) {
-  __syncthreads();
+// The last block of a pass to finish resets the tile ticket and the finished
+// count and advances the epoch, so the pass can be enqueued again without
+// another preparation launch (its successor's tag differs from every tag this
+// pass wrote).  Every block took its ticket and read the epoch before any
+// block can be last.  The timeout flag (ctr[2]) is left for diagnosis.
+KF_DEV void finish_grid(unsigned* __restrict__ ctr, unsigned tag) {
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned done = atomicAdd(ctr + 1, 1u);
-    *s_last = (done == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (*s_last) {
-    __threadfence();
-    for (long i = threadIdx.x; i < nflags; i += BLOCK) flags[i] = LB_EMPTY;
-    if (threadIdx.x == 0) {
-      ctr[0] = 0u;
-      ctr[1] = 0u;
+    if (done == gridDim.x - 1) {
+      st_relaxed(ctr + 0, 0u);
+      st_relaxed(ctr + 1, 0u);
+      st_relaxed(ctr + 3, tag);
     }
   }
 }
@@ -346,7 +355,18 @@ KF_DEV void finish_grid(int* __restrict__ flags, unsigned* __restrict__ ctr, lon
 template <int N, class R> struct St {
   R v[N];
   R m[N][N];
+  static constexpr int SIZE = N + N * N;
 };
+
+template <int N, class R, class F> KF_DEV void each(St<N, R>& x, F f) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) f(x.v[i], k++);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) f(x.m[i][j], k++);
+}
 
 template <int N, class R> KF_DEV void st_zero(St<N, R>& s) {
 #pragma unroll
@@ -378,15 +398,21 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   using E = typename Pipe::E;
   constexpr int NW = BLOCK / WAVE;
   constexpr int PS = N + N * N;
+  constexpr int ESW = E::SIZE * kWords<R>;  // tagged words per published element
+  constexpr int PSW = PS * kWords<R>;       // tagged words per published anchored state
   __shared__ E s_wt[NW];      // inclusive totals of each wavefront
   __shared__ E s_x[BLOCK];    // inclusive prefix of each thread within its wavefront
   __shared__ R s_pre[PS];     // the tile's exclusive anchored state
   __shared__ long s_tile;
-  __shared__ int s_last;
+  __shared__ unsigned s_tag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-  if (tid == 0) s_tile = (long)atomicAdd(a.ctr, 1u);
+  if (tid == 0) {
+    s_tile = (long)atomicAdd(a.ctr, 1u);
+    s_tag = ld_relaxed(a.ctr + 3) + 1u;
+  }
   __syncthreads();
   const long gt = s_tile;
+  const unsigned tag = s_tag;
   const long seq = gt / a.ntiles, t = gt - seq * a.ntiles;
   pp.bind(seq, t, tid);
   auto op = [&](const E& p, const E& q) { return pp.op(p, q); };
@@ -402,40 +428,34 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   __syncthreads();
 
   // 3. publish the tile aggregate, look back, publish the anchored prefix
+  //    (every lane of wavefront 0 holds the same values)
   const long base = seq * a.ntiles;
   if (wid == 0) {
     E tot = s_wt[0];
 #pragma unroll 1
     for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
+    St<N, R> st;
     if (t == 0) {
-      if (lane == 0) {
-        St<N, R> st;
-        pp.initial(st);
-        pp.apply(st, tot);
-        st_store(a.pre + (base + t) * PS, st);
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
+      pp.initial(st);
     } else {
-      if (lane == 0) {
-        gstore(a.agg + (base + t) * E::SIZE, tot);
-        lb_store_flag(a.flags + base + t, LB_AGG);
-      }
-      auto load_agg = [&](long idx, E& v) { gload(v, a.agg + (base + idx) * E::SIZE); };
-      auto expand = [&](long idx, E& v) {
-        St<N, R> st;
-        st_load(st, a.pre + (base + idx) * PS);
-        pp.expand(st, v);
+      tag_publish<R>(a.agg + (base + t) * ESW, tot, tag, lane);
+      if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_AGG);
+      auto load_agg = [&](long idx, E& v) {
+        tag_load<R>(v, a.agg + (base + idx) * ESW, tag, a.ctr + 2);
       };
-      E ex = lookback<E>(a.flags + base, a.ctr + 2, t, lane, op, load_agg, expand);
-      if (lane == 0) {
-        St<N, R> st;
-        pp.anchor(ex, st);
-        st_store(s_pre, st);
-        pp.apply(st, tot);
-        st_store(a.pre + (base + t) * PS, st);
-        lb_store_flag(a.flags + base + t, LB_PREFIX);
-      }
+      auto expand = [&](long idx, E& v) {
+        St<N, R> sp;
+        tag_load<R>(sp, a.pre + (base + idx) * PSW, tag, a.ctr + 2);
+        pp.expand(sp, v);
+      };
+      E ex = lookback<E>(a.flags + base, a.ctr + 2, tag, t, lane, a.lb_group, op, load_agg,
+                         expand);
+      pp.anchor(ex, st);
+      if (lane == 0) st_store(s_pre, st);
     }
+    pp.apply(st, tot);
+    tag_publish<R>(a.pre + (base + t) * PSW, st, tag, lane);
+    if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_PREFIX);
   }
   __syncthreads();
 
@@ -448,7 +468,7 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   if (lane > 0) pp.apply(st, s_x[tid - 1]);
   const bool have = (t > 0) || (tid > 0);
   pp.steps(st, have);
-  finish_grid<BLOCK>(a.flags, a.ctr, a.nseq * a.ntiles, &s_last);
+  finish_grid(a.ctr, tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -686,6 +706,48 @@ template <int N, class R> KF_DEV void load_state(const R* __restrict__ m, const 
   }
 }
 
+// Smoothing element of row k from the filter moments (x, Pk) of that row:
+// eq. prts_init2 at the last row, eq. prts_init1 elsewhere.
+template <int N, int M, class P>
+KF_DEV SElem<N, typename P::R> rts_element(const typename P::R* __restrict__ cst, long T, long k,
+                                           const typename P::R (&x)[N],
+                                           const typename P::R (&Pk)[N][N]) {
+  using R = typename P::R;
+  using LY = CL<N, M>;
+  SElem<N, R> e;
+  if (k == T - 1) {
+    set_identity(e);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      e.E[i][i] = R(0);
+      e.g[i] = x[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) e.L[i][j] = Pk[i][j];
+    }
+  } else {
+    R Fm[N][N], Qm[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        Fm[i][j] = cst[LY::F + i * N + j];
+        Qm[i][j] = cst[LY::Q + i * N + j];
+      }
+    e = smooth_element<N, P>(x, Pk, Fm, Qm);
+  }
+  return e;
+}
+
+// Element at row k of the two-filter backward scan over (a_2, ..., a_T, e):
+// a_{k+2} built from y at row k+1, the identity at the last row.
+template <int N, int M, class R>
+KF_DEV FElem<N, R> tf_element(const R* __restrict__ cst, long T, long k, const R (&yk)[M]) {
+  FElem<N, R> e;
+  if (k == T - 1) set_identity(e);
+  else e = filter_element<N, M, R>(cst, k + 1, yk);
+  return e;
+}
+
 template <int N, int M, class P, int L> struct RtsPipe {
   using R = typename P::R;
   using E = SElem<N, R>;
@@ -713,28 +775,7 @@ template <int N, int M, class P, int L> struct RtsPipe {
     if (k >= 0 && k < T) load_state<N, R>(mf, Pf, k, x, Pk);
   }
   KF_DEV E element(long k, const R (&x)[N], const R (&Pk)[N][N]) const {
-    E e;
-    if (k == T - 1) {  // eq. prts_init2
-      set_identity(e);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        e.E[i][i] = R(0);
-        e.g[i] = x[i];
-#pragma unroll
-        for (int j = 0; j < N; ++j) e.L[i][j] = Pk[i][j];
-      }
-    } else {
-      R Fm[N][N], Qm[N][N];
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          Fm[i][j] = io.cst[LY::F + i * N + j];
-          Qm[i][j] = io.cst[LY::Q + i * N + j];
-        }
-      e = smooth_element<N, P>(x, Pk, Fm, Qm);
-    }
-    return e;
+    return rts_element<N, M, P>(io.cst, T, k, x, Pk);
   }
   // Steps are walked last to first with the next (earlier) step's filter
   // moments already in flight.
@@ -836,12 +877,7 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
 #pragma unroll
     for (int c = 0; c < M; ++c) yk[c] = (k >= 0 && k + 1 < T) ? y[(k + 1) * M + c] : R(0);
   }
-  KF_DEV E element(long k, const R (&yk)[M]) const {
-    E e;
-    if (k == T - 1) set_identity(e);
-    else e = filter_element<N, M, R>(io.cst, k + 1, yk);
-    return e;
-  }
+  KF_DEV E element(long k, const R (&yk)[M]) const { return tf_element<N, M, R>(io.cst, T, k, yk); }
   KF_DEV E fold() const {
     E agg;
     set_identity(agg);

@@ -25,28 +25,49 @@ inline size_t word_bytes(int precision) { return precision == KF_PREC_F64 ? 8 : 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace regions (byte offsets from the workspace base).  The control
-// words (tile tickets, timeout flags and look-back status words of both scan
-// slots) come first and are zeroed by the preparation kernel at the start of
-// every call, so a workspace needs no initialisation and carries no state
-// from one call to the next.
+// region -- tile tickets, epochs, timeout flags, look-back status words and
+// the tagged look-back payloads of both scan slots -- comes first and is
+// zeroed by the preparation kernel at the start of every call, so a workspace
+// needs no initialisation and carries no state from one call to the next.
 struct Layout {
-  size_t ctr[2];              // [0] tile ticket, [1] finished blocks, [2] timeout flag
+  size_t ctr[2];              // [0] tile ticket, [1] finished blocks, [2] timeout flag, [3] epoch
   size_t flags[2];            // look-back status words, slot 0 forward, slot 1 backward
+  size_t agg[2];              // published tile aggregates (tagged 64-bit words)
+  size_t pre[2];              // published anchored prefixes (tagged 64-bit words)
   size_t ctrl_words;          // 32-bit words of the control region at offset 0
   size_t cst;                 // derived model quantities
-  size_t agg[2];              // published tile aggregates
-  size_t pre[2];              // published anchored prefixes
+  size_t tree[2];             // element buffers of the tree scans (Hillis-Steele: both)
+  long tree_positions;        // scan positions per sequence of the tree scans
   long max_tiles;             // tiles per sequence at the smallest tile size
   size_t total;
 };
+
+// Tiles per lane in a look-back window: one window of 64*G tiles reaches
+// back over a whole sequence of up to 512 tiles.
+inline int lookback_group(long ntiles) {
+  const long g = (ntiles + 63) / 64;
+  return (int)(g < 1 ? 1 : (g > 8 ? 8 : g));
+}
 
 inline long ntiles_for(long T, int items) {
   const long tile = (long)kBlock * items;
   return (T + tile - 1) / tile;
 }
 
-inline Layout make_layout(int nx, int ny, int precision, long T, long nseq) {
+inline bool is_tree_scan(int scan) {
+  return scan == KF_SCAN_BLELLOCH || scan == KF_SCAN_HILLIS_STEELE;
+}
+
+inline long tree_positions_for(int scan, long T) {
+  if (scan == KF_SCAN_HILLIS_STEELE) return T;
+  long p = 1;
+  while (p < T) p <<= 1;
+  return p;
+}
+
+inline Layout make_layout(int nx, int ny, int precision, int scan, long T, long nseq) {
   const size_t w = word_bytes(precision);
+  const size_t halves = w / 4;                           // tagged words per scalar
   const long n = nx, m = ny;
   Layout L{};
   L.max_tiles = ntiles_for(T, items_min(nx));
@@ -55,19 +76,34 @@ inline Layout make_layout(int nx, int ny, int precision, long T, long nseq) {
       10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(nx) * n * m;
   const size_t elem_words = 3 * n * n + 2 * n;           // largest element (filtering)
   const size_t pre_words = n + n * n;
-  L.ctr[0] = 0;
-  L.ctr[1] = 4 * sizeof(unsigned);
-  L.flags[0] = 8 * sizeof(unsigned);
-  L.flags[1] = L.flags[0] + nt * sizeof(int);
-  L.ctrl_words = (L.flags[1] + nt * sizeof(int)) / 4;
-  size_t off = align256(L.ctrl_words * 4);
-  L.cst = off;
-  off = align256(off + cst_words * w);
+  size_t off = 0;
+  for (int s = 0; s < 2; ++s) {
+    L.ctr[s] = off;
+    off += 4 * sizeof(unsigned);
+  }
+  for (int s = 0; s < 2; ++s) {
+    L.flags[s] = off;
+    off += nt * sizeof(int);
+  }
+  off = (off + 7) & ~size_t(7);
   for (int s = 0; s < 2; ++s) {
     L.agg[s] = off;
-    off = align256(off + nt * elem_words * w);
+    off += nt * elem_words * halves * 8;
     L.pre[s] = off;
-    off = align256(off + nt * pre_words * w);
+    off += nt * pre_words * halves * 8;
+  }
+  L.ctrl_words = off / 4;
+  off = align256(off);
+  L.cst = off;
+  off = align256(off + cst_words * w);
+  L.tree[0] = L.tree[1] = off;
+  if (is_tree_scan(scan)) {
+    L.tree_positions = tree_positions_for(scan, T);
+    const size_t buf = (size_t)nseq * elem_words * (size_t)L.tree_positions * w;
+    L.tree[0] = off;
+    off = align256(off + buf);
+    L.tree[1] = off;
+    if (scan == KF_SCAN_HILLIS_STEELE) off = align256(off + buf);
   }
   L.total = off;
   return L;

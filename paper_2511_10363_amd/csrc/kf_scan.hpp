@@ -27,14 +27,6 @@ template <class E> KF_DEV E bcast_lane0(E x) {
   return x;
 }
 
-// Flat global-memory access to an element (SIZE scalars, storage order).
-template <class E, class R> KF_DEV void gload(E& x, const R* __restrict__ p) {
-  each(x, [&](R& v, int k) { v = p[k]; });
-}
-template <class E, class R> KF_DEV void gstore(R* __restrict__ p, E& x) {
-  each(x, [&](R& v, int k) { p[k] = v; });
-}
-
 // Inclusive scan across the 64 lanes of a wavefront (Hillis-Steele over lanes,
 // Algorithm 1 at wavefront scale): after it, lane l holds x_0 .. x_l.
 template <class E, class Op> KF_DEV void wave_inclusive_scan(E& x, int lane, Op op) {
@@ -45,69 +37,171 @@ template <class E, class Op> KF_DEV void wave_inclusive_scan(E& x, int lane, Op 
   }
 }
 
-// Look-back status words.
+// ---------------------------------------------------------------------------
+// Publication of tile results between workgroups.
+//
+// On gfx950 every agent-scope acquire or release costs a whole-L2 operation
+// (buffer_inv sc1 / buffer_wbl2 sc1 on the XCD's cache), which a spinning
+// look-back would issue on every poll.  Instead every published word carries
+// the pass's tag and is written and read with relaxed agent-scope atomics
+// (plain sc1 accesses, coherent across XCDs, no cache maintenance):
+//   status word  (tag << 2) | status            32 bit
+//   payload      (tag << 32) | 32 value bits    64 bit, one per 32-bit half
+// A reader accepts a word only when its tag matches, so no ordering between
+// payload and status stores is needed: a status seen early only means the
+// payload words are still on their way, and the reader polls them too.
+// The tag of a pass is one more than the epoch word left by the previous
+// pass (zero after the preparation kernel clears the control region).
+// ---------------------------------------------------------------------------
+using u64 = unsigned long long;
+
+template <class R> constexpr int kWords = (int)(sizeof(R) / 4);  // 32-bit halves per scalar
+
+KF_DEV u64 ld_relaxed(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+KF_DEV void st_relaxed(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+KF_DEV unsigned ld_relaxed(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+KF_DEV void st_relaxed(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+KF_DEV unsigned half_bits(float v, int) { return __float_as_uint(v); }
+KF_DEV unsigned half_bits(double v, int h) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return h ? (unsigned)(b >> 32) : (unsigned)b;
+}
+
+// The lanes of a wavefront publish x together: lane l writes words l, l+64, ...
+// (word w holds half w % kWords of scalar w / kWords, in storage order).
+template <class R, class E> KF_DEV void tag_publish(u64* __restrict__ p, E& x, unsigned tag,
+                                                    int lane) {
+  constexpr int NW = E::SIZE * kWords<R>;
+#pragma unroll
+  for (int w0 = 0; w0 < NW; w0 += WAVE) {
+    const int w = w0 + lane;
+    if (w < NW) {
+      const int si = w / kWords<R>, h = w % kWords<R>;
+      R val = R(0);
+      each(x, [&](R& v, int k) { val = (k == si) ? v : val; });
+      st_relaxed(p + w, ((u64)tag << 32) | (u64)half_bits(val, h));
+    }
+  }
+}
+
+// One attempt to read a whole published element into this lane; false if any
+// word does not carry the tag yet.
+template <class R, class E> KF_DEV bool tag_try_load(E& x, const u64* __restrict__ p,
+                                                     unsigned tag) {
+  bool ok = true;
+  each(x, [&](R& v, int k) {
+    if constexpr (sizeof(R) == 4) {
+      const u64 w = ld_relaxed(p + k);
+      ok = ok & ((unsigned)(w >> 32) == tag);
+      v = __uint_as_float((unsigned)w);
+    } else {
+      const u64 lo = ld_relaxed(p + 2 * k), hi = ld_relaxed(p + 2 * k + 1);
+      ok = ok & ((unsigned)(lo >> 32) == tag) & ((unsigned)(hi >> 32) == tag);
+      v = __longlong_as_double((long long)(((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull)));
+    }
+  });
+  return ok;
+}
+
+// Look-back status values.
 constexpr int LB_EMPTY = 0;
 constexpr int LB_AGG = 1;     // the tile's own aggregate is published
 constexpr int LB_PREFIX = 2;  // the tile's inclusive (anchored) prefix is published
 
-KF_DEV int lb_load_flag(const int* f) {
-  return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-KF_DEV void lb_store_flag(int* f, int v) {
-  __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Bounded wait for a predecessor's status word.  A legitimate wait lasts as
-// long as one tile's fold (microseconds); the bound (~2^24 polls, about a
-// second) only guarantees that every wave exits even if a predecessor never
-// publishes.  On expiry the wait reports LB_PREFIX, the caller continues with
-// whatever payload is there, and the sticky error word *err is raised so the
-// host can tell the result is invalid.
+// Bounded waits.  A legitimate wait lasts as long as one tile's fold
+// (microseconds); the bound (~2^24 polls, about a second) only guarantees
+// that every wave exits even if a predecessor never publishes.  On expiry the
+// wait gives up, the caller continues with whatever it read, and the sticky
+// error word *err is raised so the host can tell the result is invalid.
 constexpr unsigned LB_SPIN_LIMIT = 1u << 24;
-KF_DEV int lb_wait_flag(const int* f, unsigned* err) {
-  int v = lb_load_flag(f);
+
+KF_DEV void lb_publish_flag(int* f, unsigned tag, int status) {
+  __hip_atomic_store(f, (int)((tag << 2) | (unsigned)status), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+KF_DEV int lb_wait_flag(const int* f, unsigned tag, unsigned* err) {
+  const unsigned want = tag & 0x3fffffffu;
   unsigned spins = 0;
-  while (v == LB_EMPTY) {
-    __builtin_amdgcn_s_sleep(1);
-    v = lb_load_flag(f);
+  while (true) {
+    const unsigned v =
+        (unsigned)__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((v >> 2) == want && (v & 3u) != 0u) return (int)(v & 3u);
     if (++spins >= LB_SPIN_LIMIT) {
       atomicOr(err, 1u);
       return LB_PREFIX;
     }
+    __builtin_amdgcn_s_sleep(1);
   }
-  return v;
+}
+template <class R, class E> KF_DEV void tag_load(E& x, const u64* __restrict__ p, unsigned tag,
+                                                 unsigned* err) {
+  unsigned spins = 0;
+  while (!tag_try_load<R>(x, p, tag)) {
+    if (++spins >= LB_SPIN_LIMIT) {
+      atomicOr(err, 1u);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
 }
 
 // Windowed look-back executed by one full wavefront.
 //
-// Tile `t` (scan order) needs the combination of all tiles before it.  Lane l
-// inspects tile t-1-l-64w of window w; the nearest tile whose anchored prefix
-// is published ends the search.  The window's elements are reduced with a
-// lane tree in scan order (higher lane = earlier), skipping levels that no
-// lane needs, and windows are folded right to left.  Returns, in every lane,
-// the exclusive prefix of tile t as an element (the anchored prefix is
-// expanded with `expand`).
+// Tile `t` (scan order) needs the combination of all tiles before it.  A
+// window covers 64*G tiles: lane l takes the G consecutive tiles
+// j-lG-G+1 .. j-lG (j = t-1 for the first window) and waits for their status
+// words nearest first; the nearest tile in the window whose anchored prefix is
+// published ends the search.  Each lane folds its tiles in scan order (the
+// published prefix, expanded with `expand`, then the later aggregates), the
+// lanes are reduced with a tree in scan order (higher lane = earlier),
+// skipping levels that no lane needs, and windows are folded right to left.
+// G > 1 trades G-1 serial combines per lane for fewer window hops when many
+// tiles publish their aggregates at about the same time.  Returns, in every
+// lane, the exclusive prefix of tile t as an element.
 //   load_agg(idx, E&)    : element published with LB_AGG by tile idx
 //   expand(idx, E&)      : element form of tile idx's anchored prefix
 template <class E, class Op, class LoadAgg, class Expand>
-KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, long t, int lane, Op op,
-                  LoadAgg load_agg, Expand expand) {
+KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, long t, int lane,
+                  int G, Op op, LoadAgg load_agg, Expand expand) {
   E acc;
   bool have = false;
   long j = t - 1;
 #pragma unroll 1
   while (true) {
-    const long idx = j - lane;
-    int f = LB_PREFIX;  // lanes before tile 0 behave as "past the anchor"
-    if (idx >= 0) f = lb_wait_flag(flags + idx, err);
-    const unsigned long long pm = __ballot(f == LB_PREFIX && idx >= 0);
+    const long hi = j - (long)lane * G;  // this lane's latest tile
+    int gp = G;                           // offset of its nearest published prefix
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+      const long idx = hi - g;
+      if (idx < 0) break;
+      if (lb_wait_flag(flags + idx, tag, err) == LB_PREFIX) {
+        gp = g;
+        break;
+      }
+    }
+    const unsigned long long pm = __ballot(gp < G);
     const int lp = pm ? (__ffsll((long long)pm) - 1) : WAVE - 1;  // last lane taking part
     E v;
-    if (lane < lp) {
-      load_agg(idx, v);
-    } else if (lane == lp) {
-      if (pm) expand(idx, v); else load_agg(idx, v);
-    } else {
-      set_identity(v);
+    set_identity(v);
+    if (lane <= lp) {
+      const bool anchored = (lane == lp) && pm;
+      int g = anchored ? gp - 1 : G - 1;
+      if (anchored) expand(hi - gp, v); else load_agg(hi - g--, v);
+#pragma unroll 1
+      for (; g >= 0; --g) {
+        E u;
+        load_agg(hi - g, u);
+        v = op(v, u);
+      }
     }
     // lane tree: at level s, lane l (multiple of 2s) folds in lane l+s (earlier)
 #pragma unroll 1
@@ -119,7 +213,7 @@ KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, long t, int lane
     acc = have ? op(w, acc) : w;
     have = true;
     if (pm) break;
-    j -= WAVE;
+    j -= (long)WAVE * G;
   }
   return acc;
 }

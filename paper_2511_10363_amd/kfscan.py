@@ -47,7 +47,7 @@ class KfScanError(RuntimeError):
 _lib = None
 _lock = threading.Lock()
 EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_size",
-           "kf_workspace_clear", "kf_workspace_timed_out", "kf_filter", "kf_smooth_rts",
+           "kf_workspace_clear", "kf_workspace_timed_out", "kf_device_copy", "kf_filter", "kf_smooth_rts",
            "kf_smooth_twofilter", "kf_prepare", "kf_pass_filter", "kf_pass_rts",
            "kf_pass_twofilter")
 STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
         lib.kf_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         lib.kf_workspace_clear.restype = ctypes.c_int
         lib.kf_workspace_clear.argtypes = [_VOIDP, ctypes.c_size_t, _VOIDP]
+        lib.kf_device_copy.restype = ctypes.c_int
+        lib.kf_device_copy.argtypes = [_VOIDP, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_workspace_timed_out.restype = ctypes.c_int
         lib.kf_workspace_timed_out.argtypes = [P, _VOIDP, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_int32), _VOIDP]
@@ -255,6 +257,19 @@ class Plan:
 
     def outputs(self):
         return (self.keep["m_filt"], self.keep["P_filt"], self.m_s, self.P_s)
+
+
+def device_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
+    """dst[:] = src[:] (same byte size, contiguous, on one GPU) with the library's
+    plain streaming copy kernel, on the current stream."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise KfScanError("device_copy needs contiguous GPU tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("device_copy: size mismatch")
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    _check(load_library().kf_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream),
+           "kf_device_copy")
 
 
 def supported(nx: int, ny: int, precision: str = "f32") -> bool:

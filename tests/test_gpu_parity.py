@@ -61,9 +61,11 @@ def _check(entry, model, y, prec, tol=None, scan="auto"):
 
 
 SCAN_KINDS = ["lookback", "lookback_generic"]
+TREE_KINDS = ["blelloch", "hillis_steele"]    # one kernel per tree level (Algorithms 1, 2)
+ALL_KINDS = SCAN_KINDS + TREE_KINDS
 
 
-@pytest.mark.parametrize("scan", SCAN_KINDS)
+@pytest.mark.parametrize("scan", ALL_KINDS)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
 def test_tracking_T1000(entry, prec, scan):
@@ -72,7 +74,7 @@ def test_tracking_T1000(entry, prec, scan):
     _check(entry, model, y, prec, scan=scan)
 
 
-@pytest.mark.parametrize("scan", SCAN_KINDS)
+@pytest.mark.parametrize("scan", ALL_KINDS)
 @pytest.mark.parametrize("T", [1, 2, 3, 7, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096,
                                4097, 6000, 8193, 12289])
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
@@ -83,7 +85,7 @@ def test_ragged_lengths_f64(entry, T, scan):
     _check(entry, model, y, "f64", scan=scan)
 
 
-@pytest.mark.parametrize("scan", SCAN_KINDS)
+@pytest.mark.parametrize("scan", ALL_KINDS)
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 4)])
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
@@ -94,15 +96,17 @@ def test_shapes_stable_models(entry, prec, nx, ny, scan):
     _check(entry, model, y, prec, scan=scan)
 
 
+@pytest.mark.parametrize("scan", ALL_KINDS)
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
-def test_batch_of_sequences(entry):
+def test_batch_of_sequences(entry, scan):
     """nseq sequences sharing the model in one launch equal separate runs."""
+    _say("batch", entry, scan)
     model = W.cv_model()
     rng = np.random.default_rng(4)
     ys = np.stack([W.simulate(model, 3000, rng) for _ in range(3)])
     k = kfscan()
     out = {"filter": k.filter, "rts": k.smooth_rts, "tf": k.smooth_twofilter}[entry](
-        to_dev(model, "f64"), y_dev(ys, "f64"), precision="f64")
+        to_dev(model, "f64"), y_dev(ys, "f64"), precision="f64", scan=scan)
     torch.cuda.synchronize()
     for s in range(3):
         ref = _reference(entry, model, ys[s], "f64")
@@ -127,6 +131,16 @@ def test_workspace_reuse_is_deterministic():
 def test_full_size_T_2_20(prec, scan):
     """The benchmark workload: tracking model, T = 2^20, filter + RTS smoother,
     every output compared with the oracle."""
+    T = 1 << 20
+    model, y = W.tracking(T, seed=20251110)
+    errs = _check("rts", model, y, prec, scan=scan)
+    _say("errors", errs)
+
+
+@pytest.mark.parametrize("scan", TREE_KINDS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_tree_scans_T_2_20(prec, scan):
+    """The benchmark workload through the one-kernel-per-level scans."""
     T = 1 << 20
     model, y = W.tracking(T, seed=20251110)
     errs = _check("rts", model, y, prec, scan=scan)
