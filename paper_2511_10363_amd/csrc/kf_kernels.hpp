@@ -403,6 +403,8 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   __shared__ E s_wt[NW];      // inclusive totals of each wavefront
   __shared__ E s_x[BLOCK];    // inclusive prefix of each thread within its wavefront
   __shared__ R s_pre[PS];     // the tile's exclusive anchored state
+  __shared__ E s_part[NW];    // look-back: wavefront partials of a window
+  __shared__ int s_lp[NW];    // look-back: first lane of each wavefront with a published prefix
   __shared__ long s_tile;
   __shared__ unsigned s_tag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
@@ -427,45 +429,90 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   }
   __syncthreads();
 
-  // 3. publish the tile aggregate, look back, publish the anchored prefix
-  //    (every lane of wavefront 0 holds the same values)
+  // 3. publish (wavefront 0; every lane holds the same values), look back
+  //    (whole workgroup), publish the anchored inclusive prefix (wavefront 0).
+  //    If a wavefront total is an anchor (decay_is_zero), the tile's anchored
+  //    inclusive prefix follows from it and the later totals alone, so it is
+  //    published at once, before the look-back; so is tile 0's, and so is
+  //    the prefix of a tile whose aggregate is itself an anchor.  Otherwise
+  //    the tile aggregate is published first and the prefix after the look-back.
   const long base = seq * a.ntiles;
+  E tot;
+  bool early = false;
   if (wid == 0) {
-    E tot = s_wt[0];
+    int wa = -1;
 #pragma unroll 1
-    for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
-    St<N, R> st;
-    if (t == 0) {
-      pp.initial(st);
+    for (int w = NW - 1; w >= 0; --w)
+      if (decay_is_zero(s_wt[w])) {
+        wa = w;
+        break;
+      }
+    if (t == 0 || wa >= 0) {
+      St<N, R> st;
+      if (wa >= 0) pp.anchor(s_wt[wa], st); else pp.initial(st);
+#pragma unroll 1
+      for (int w = wa + 1; w < NW; ++w) pp.apply(st, s_wt[w]);
+      tag_publish<R>(a.pre + (base + t) * PSW, st, tag, lane);
+      if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_PREFIX);
+      early = true;
     } else {
-      tag_publish<R>(a.agg + (base + t) * ESW, tot, tag, lane);
-      if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_AGG);
-      auto load_agg = [&](long idx, E& v) {
-        tag_load<R>(v, a.agg + (base + idx) * ESW, tag, a.ctr + 2);
-      };
-      auto expand = [&](long idx, E& v) {
-        St<N, R> sp;
-        tag_load<R>(sp, a.pre + (base + idx) * PSW, tag, a.ctr + 2);
-        pp.expand(sp, v);
-      };
-      E ex = lookback<E>(a.flags + base, a.ctr + 2, tag, t, lane, a.lb_group, op, load_agg,
-                         expand);
-      pp.anchor(ex, st);
-      if (lane == 0) st_store(s_pre, st);
+      tot = s_wt[0];
+#pragma unroll 1
+      for (int w = 1; w < NW; ++w) tot = op(tot, s_wt[w]);
+      if (decay_is_zero(tot)) {
+        St<N, R> st;
+        pp.anchor(tot, st);
+        tag_publish<R>(a.pre + (base + t) * PSW, st, tag, lane);
+        if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_PREFIX);
+        early = true;
+      } else {
+        tag_publish<R>(a.agg + (base + t) * ESW, tot, tag, lane);
+        if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_AGG);
+      }
     }
-    pp.apply(st, tot);
-    tag_publish<R>(a.pre + (base + t) * PSW, st, tag, lane);
-    if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_PREFIX);
+  }
+  E ex;
+  if (t > 0) {
+    auto load_agg = [&](long idx, E& v) {
+      tag_load<R>(v, a.agg + (base + idx) * ESW, tag, a.ctr + 2);
+    };
+    auto expand = [&](long idx, E& v) {
+      St<N, R> sp;
+      tag_load<R>(sp, a.pre + (base + idx) * PSW, tag, a.ctr + 2);
+      pp.expand(sp, v);
+    };
+    ex = lookback<BLOCK, E>(a.flags + base, a.ctr + 2, tag, t, a.lb_group, op, load_agg, expand,
+                            s_part, s_lp);
+  }
+  if (wid == 0 && t > 0) {
+    St<N, R> st;
+    pp.anchor(ex, st);
+    if (lane == 0) st_store(s_pre, st);
+    if (!early) {
+      pp.apply(st, tot);
+      tag_publish<R>(a.pre + (base + t) * PSW, st, tag, lane);
+      if (lane == 0) lb_publish_flag(a.flags + base + t, tag, LB_PREFIX);
+    }
   }
   __syncthreads();
 
   // 4. this thread's exclusive anchored state: the tile's, then the totals
-  //    of the earlier wavefronts, then the earlier lanes of this wavefront
+  //    of the earlier wavefronts, then the earlier lanes of this wavefront,
+  //    each starting over from the last anchor among them
   St<N, R> st;
-  if (t > 0) st_load(st, s_pre); else pp.initial(st);
+  int ws = -1;
 #pragma unroll 1
-  for (int w = 0; w < wid; ++w) pp.apply(st, s_wt[w]);
-  if (lane > 0) pp.apply(st, s_x[tid - 1]);
+  for (int w = 0; w < wid; ++w)
+    if (decay_is_zero(s_wt[w])) ws = w;
+  if (ws >= 0) pp.anchor(s_wt[ws], st);
+  else if (t > 0) st_load(st, s_pre);
+  else pp.initial(st);
+#pragma unroll 1
+  for (int w = ws + 1; w < wid; ++w) pp.apply(st, s_wt[w]);
+  if (lane > 0) {
+    if (decay_is_zero(s_x[tid - 1])) pp.anchor(s_x[tid - 1], st);
+    else pp.apply(st, s_x[tid - 1]);
+  }
   const bool have = (t > 0) || (tid > 0);
   pp.steps(st, have);
   finish_grid(a.ctr, tag);

@@ -72,6 +72,32 @@ template <int N, class R, class F> KF_DEV void each(SElem<N, R>& x, F f) {
     for (int j = 0; j < N; ++j) f(x.L[i][j], k++);
 }
 
+// An element whose decay matrix (A of a filtering element, E of a smoothing
+// element) is exactly zero is an anchor: by Lemma 1 (resp. Lemma 2), whatever
+// is combined before it in scan order enters the anchored part of the result
+// -- (b, C), (g, L), or (eta, J) in the reversed two-filter scan -- only
+// through products with that zero matrix, so those parts equal the
+// element's own.  The first filtering element (A_1 = 0, eq. pkf_init2) and the
+// last smoothing element (E_T = 0, eq. prts_init2) are anchors by
+// construction; long aggregates of a stable model become anchors once their
+// decay matrix underflows to zero.
+template <int N, class R> KF_DEV bool decay_is_zero(const FElem<N, R>& x) {
+  bool z = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) z = z & (x.A[i][j] == R(0));
+  return z;
+}
+template <int N, class R> KF_DEV bool decay_is_zero(const SElem<N, R>& x) {
+  bool z = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) z = z & (x.E[i][j] == R(0));
+  return z;
+}
+
 // Two-sided identities (I, 0, 0, 0, 0) and (I, 0, 0).
 template <int N, class R> KF_DEV void set_identity(FElem<N, R>& x) {
   each(x, [](R& v, int) { v = R(0); });

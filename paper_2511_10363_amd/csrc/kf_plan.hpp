@@ -42,11 +42,11 @@ struct Layout {
   size_t total;
 };
 
-// Tiles per lane in a look-back window: one window of 64*G tiles reaches
-// back over a whole sequence of up to 512 tiles.
+// Tiles per thread in a look-back window: one window of 256*G tiles reaches
+// back over a whole sequence of up to 1024 tiles.
 inline int lookback_group(long ntiles) {
-  const long g = (ntiles + 63) / 64;
-  return (int)(g < 1 ? 1 : (g > 8 ? 8 : g));
+  const long g = (ntiles + kBlock - 1) / kBlock;
+  return (int)(g < 1 ? 1 : (g > 4 ? 4 : g));
 }
 
 inline long ntiles_for(long T, int items) {

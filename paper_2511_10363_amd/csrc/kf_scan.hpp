@@ -154,31 +154,47 @@ template <class R, class E> KF_DEV void tag_load(E& x, const u64* __restrict__ p
   }
 }
 
-// Windowed look-back executed by one full wavefront.
+// Windowed look-back executed by the whole workgroup (BLOCK threads).
 //
 // Tile `t` (scan order) needs the combination of all tiles before it.  A
-// window covers 64*G tiles: lane l takes the G consecutive tiles
-// j-lG-G+1 .. j-lG (j = t-1 for the first window) and waits for their status
+// window covers BLOCK*G tiles: thread i takes the G consecutive tiles
+// j-iG-G+1 .. j-iG (j = t-1 for the first window) and waits for their status
 // words nearest first; the nearest tile in the window whose anchored prefix is
-// published ends the search.  Each lane folds its tiles in scan order (the
-// published prefix, expanded with `expand`, then the later aggregates), the
-// lanes are reduced with a tree in scan order (higher lane = earlier),
-// skipping levels that no lane needs, and windows are folded right to left.
-// G > 1 trades G-1 serial combines per lane for fewer window hops when many
-// tiles publish their aggregates at about the same time.  Returns, in every
-// lane, the exclusive prefix of tile t as an element.
+// published ends the search.  Each thread folds its tiles in scan order (the
+// published prefix, expanded with `expand`, then the later aggregates), each
+// wavefront reduces its lanes with a tree in scan order (higher lane =
+// earlier), skipping levels no lane needs, the wavefront partials are folded
+// through LDS (higher wavefront = earlier), and windows are folded right to
+// left.  Every thread polls and loads its own tiles at once, so a window costs
+// one round of memory latency.  Tile t-1 is looked at first on its own: if its
+// anchored prefix is already published, that is the answer.  Block-uniform control flow: every thread of
+// the workgroup must call it.  Returns, in every thread, the exclusive prefix
+// of tile t as an element.
 //   load_agg(idx, E&)    : element published with LB_AGG by tile idx
 //   expand(idx, E&)      : element form of tile idx's anchored prefix
-template <class E, class Op, class LoadAgg, class Expand>
-KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, long t, int lane,
-                  int G, Op op, LoadAgg load_agg, Expand expand) {
+//   s_part, s_lp         : LDS scratch, BLOCK/64 entries each
+template <int BLOCK, class E, class Op, class LoadAgg, class Expand>
+KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, long t, int G, Op op,
+                  LoadAgg load_agg, Expand expand, E* s_part, int* s_lp) {
+  constexpr int NW = BLOCK / WAVE;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+  // fast path: the nearest predecessor has published its anchored prefix
+  if (tid == 0) s_lp[0] = lb_wait_flag(flags + (t - 1), tag, err);
+  __syncthreads();
+  const int f1 = s_lp[0];
+  __syncthreads();
+  if (f1 == LB_PREFIX) {
+    E v;
+    expand(t - 1, v);
+    return v;
+  }
   E acc;
   bool have = false;
   long j = t - 1;
 #pragma unroll 1
   while (true) {
-    const long hi = j - (long)lane * G;  // this lane's latest tile
-    int gp = G;                           // offset of its nearest published prefix
+    const long hi = j - (long)tid * G;  // this thread's latest tile
+    int gp = G;                          // offset of its nearest published prefix
 #pragma unroll 1
     for (int g = 0; g < G; ++g) {
       const long idx = hi - g;
@@ -189,11 +205,18 @@ KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, lo
       }
     }
     const unsigned long long pm = __ballot(gp < G);
-    const int lp = pm ? (__ffsll((long long)pm) - 1) : WAVE - 1;  // last lane taking part
+    if (lane == 0) s_lp[wid] = pm ? (__ffsll((long long)pm) - 1) : WAVE;
+    __syncthreads();
+    int first = BLOCK;  // first thread (nearest tiles first) holding a published prefix
+#pragma unroll
+    for (int w = NW - 1; w >= 0; --w)
+      if (s_lp[w] < WAVE) first = w * WAVE + s_lp[w];
+    const bool found = first < BLOCK;
+    const int last = found ? first : BLOCK - 1;  // last thread taking part
     E v;
     set_identity(v);
-    if (lane <= lp) {
-      const bool anchored = (lane == lp) && pm;
+    if (tid <= last) {
+      const bool anchored = (tid == first);
       int g = anchored ? gp - 1 : G - 1;
       if (anchored) expand(hi - gp, v); else load_agg(hi - g--, v);
 #pragma unroll 1
@@ -203,17 +226,24 @@ KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, lo
         v = op(v, u);
       }
     }
-    // lane tree: at level s, lane l (multiple of 2s) folds in lane l+s (earlier)
+    // wavefront tree: at level s, lane l (multiple of 2s) folds in lane l+s (earlier)
+    const int lw = last - wid * WAVE;  // last lane of this wavefront taking part
 #pragma unroll 1
-    for (int s = 1; s <= lp; s <<= 1) {
+    for (int s = 1; s <= lw && s < WAVE; s <<= 1) {
       E u = shfl_down(v, s);
-      if ((lane & (2 * s - 1)) == 0 && lane + s <= lp) v = op(u, v);
+      if ((lane & (2 * s - 1)) == 0 && lane + s <= lw) v = op(u, v);
     }
-    E w = bcast_lane0(v);
+    if (lane == 0 && lw >= 0) s_part[wid] = v;
+    __syncthreads();
+    const int nw = last / WAVE + 1;  // wavefronts taking part
+    E w = s_part[nw - 1];
+#pragma unroll 1
+    for (int q = nw - 2; q >= 0; --q) w = op(w, s_part[q]);
     acc = have ? op(w, acc) : w;
     have = true;
-    if (pm) break;
-    j -= (long)WAVE * G;
+    __syncthreads();  // s_part and s_lp are reused by the next window
+    if (found) break;
+    j -= (long)BLOCK * G;
   }
   return acc;
 }
