@@ -713,16 +713,37 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
 #pragma unroll
       for (int j = 0; j < M; ++j) Rm[i][j] = io.cst[LY::Rm + i * M + j];
     }
+    // outputs leave in whole 128-byte lines where the sizes allow: the means
+    // of MG consecutive steps, the covariances of PG consecutive steps
+    constexpr int MG = (N * (int)sizeof(R) <= 128 && 128 % (N * (int)sizeof(R)) == 0 &&
+                        L % (128 / (N * (int)sizeof(R))) == 0) ? 128 / (N * (int)sizeof(R)) : 1;
+    constexpr int PG = (N * N * (int)sizeof(R) <= 128 && 128 % (N * N * (int)sizeof(R)) == 0 &&
+                        L % (128 / (N * N * (int)sizeof(R))) == 0) ? 128 / (N * N * (int)sizeof(R)) : 1;
+    R ov[MG][N], om[PG][N][N];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const long k = k0 + i;
-      if (k < T) {
-        kf_step<N, M, P>(st.v, st.m, F, Q, H, Rm, yv[i]);
+      if (k < T) kf_step<N, M, P>(st.v, st.m, F, Q, H, Rm, yv[i]);
+      copy_vec<N, R>(st.v, ov[i % MG]);
+      copy_mat<N, N, R>(st.m, om[i % PG]);
+      if (i % PG == PG - 1) {
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-          mo[k * N + r] = st.v[r];
+        for (int j = 0; j < PG; ++j) {
+          const long kj = k - (PG - 1) + j;
+          if (kj < T)
 #pragma unroll
-          for (int cc = 0; cc < N; ++cc) Po[k * N * N + r * N + cc] = st.m[r][cc];
+            for (int r = 0; r < N; ++r)
+#pragma unroll
+              for (int cc = 0; cc < N; ++cc) Po[kj * N * N + r * N + cc] = om[j][r][cc];
+        }
+      }
+      if (i % MG == MG - 1) {
+#pragma unroll
+        for (int j = 0; j < MG; ++j) {
+          const long kj = k - (MG - 1) + j;
+          if (kj < T)
+#pragma unroll
+            for (int r = 0; r < N; ++r) mo[kj * N + r] = ov[j][r];
         }
       }
     }
@@ -795,7 +816,7 @@ KF_DEV FElem<N, R> tf_element(const R* __restrict__ cst, long T, long k, const R
   return e;
 }
 
-template <int N, int M, class P, int L> struct RtsPipe {
+template <int N, int M, class P, int L, int B> struct RtsPipe {
   using R = typename P::R;
   using E = SElem<N, R>;
   using LY = CL<N, M>;
@@ -824,21 +845,67 @@ template <int N, int M, class P, int L> struct RtsPipe {
   KF_DEV E element(long k, const R (&x)[N], const R (&Pk)[N][N]) const {
     return rts_element<N, M, P>(io.cst, T, k, x, Pk);
   }
-  // Steps are walked last to first with the next (earlier) step's filter
-  // moments already in flight.
-  KF_DEV E fold() const {
+  // Steps are walked last to first in groups of PG consecutive rows whose
+  // covariances fill one 128-byte line (two rows at nx = 4 in FP32), with the
+  // next (earlier) group already in flight, so each line is fetched once and
+  // consumed at once.
+  // In FP32 a thread's L filtered means (one 128-byte line at nx = 4) are
+  // read once into an LDS column of its own, serve both walks, and are
+  // overwritten in place by the smoothed means, which leave as one line.
+  static constexpr int PG = (N * N * (int)sizeof(R) <= 64 && L % 2 == 0) ? 2 : 1;
+  static constexpr int NG = L / PG;
+  static constexpr bool MLDS = (sizeof(R) == 4);
+  R* ms;  // this thread's column: row i, component c at ms[(i * N + c) * B]
+  KF_DEV void load_group(long kb, R (&x)[PG][N], R (&Pk)[PG][N][N]) const {
+#pragma unroll
+    for (int i = 0; i < PG; ++i) {
+      const long k = kb + i;
+      if (k >= 0 && k < T) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          if (!MLDS) x[i][r] = mf[k * N + r];
+#pragma unroll
+          for (int c = 0; c < N; ++c) Pk[i][r][c] = Pf[k * N * N + r * N + c];
+        }
+      }
+    }
+  }
+  KF_DEV void mean_rows(long kb, int ib, R (&x)[PG][N]) const {
+    if (MLDS) {
+#pragma unroll
+      for (int i = 0; i < PG; ++i)
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[i][r] = ms[((ib + i) * N + r) * B];
+    }
+  }
+  KF_DEV E fold() {
+    if (MLDS) {
+      __shared__ R s_mean[MLDS ? L * N * B : 1];
+      ms = s_mean + threadIdx.x;
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int r = 0; r < N; ++r) ms[(i * N + r) * B] = (k0 + i < T) ? mf[(k0 + i) * N + r] : R(0);
+    }
     E agg;
     set_identity(agg);
-    R xn[N], Pn[N][N];
-    load(k0 + L - 1, xn, Pn);
+    R xn[PG][N], Pn[PG][N][N];
+    load_group(k0 + (NG - 1) * PG, xn, Pn);
 #pragma unroll 1
-    for (int i = L - 1; i >= 0; --i) {
-      const long k = k0 + i;
-      R x[N], Pk[N][N];
-      copy_vec<N, R>(xn, x);
-      copy_mat<N, N, R>(Pn, Pk);
-      load(k - 1, xn, Pn);
-      if (k < T) agg = scombine<N, P>(element(k, x, Pk), agg);
+    for (int g = NG - 1; g >= 0; --g) {
+      R x[PG][N], Pk[PG][N][N];
+#pragma unroll
+      for (int i = 0; i < PG; ++i) {
+        copy_vec<N, R>(xn[i], x[i]);
+        copy_mat<N, N, R>(Pn[i], Pk[i]);
+      }
+      if (g > 0) load_group(k0 + (g - 1) * PG, xn, Pn);
+      mean_rows(k0 + g * PG, g * PG, x);
+#pragma unroll
+      for (int i = PG - 1; i >= 0; --i) {
+        const long k = k0 + g * PG + i;
+        if (k < T) agg = scombine<N, P>(element(k, x[i], Pk[i]), agg);
+      }
     }
     return agg;
   }
@@ -858,24 +925,53 @@ template <int N, int M, class P, int L> struct RtsPipe {
       for (int j = 0; j < N; ++j) v.L[i][j] = st.m[i][j];
     }
   }
+  // Same grouping as fold(); a group's outputs are written together, in row
+  // order, once its rows are done.
   KF_DEV void steps(St<N, R>& st, bool) const {
-    R xn[N], Pn[N][N];
-    load(k0 + L - 1, xn, Pn);
+    R xn[PG][N], Pn[PG][N][N];
+    load_group(k0 + (NG - 1) * PG, xn, Pn);
 #pragma unroll 1
-    for (int i = L - 1; i >= 0; --i) {
-      const long k = k0 + i;
-      R x[N], Pk[N][N];
-      copy_vec<N, R>(xn, x);
-      copy_mat<N, N, R>(Pn, Pk);
-      load(k - 1, xn, Pn);
-      if (k >= T) continue;
-      sapply<N, P>(element(k, x, Pk), st.v, st.m);
+    for (int g = NG - 1; g >= 0; --g) {
+      R x[PG][N], Pk[PG][N][N];
 #pragma unroll
-      for (int r = 0; r < N; ++r) {
-        mo[k * N + r] = st.v[r];
-#pragma unroll
-        for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.m[r][c];
+      for (int i = 0; i < PG; ++i) {
+        copy_vec<N, R>(xn[i], x[i]);
+        copy_mat<N, N, R>(Pn[i], Pk[i]);
       }
+      if (g > 0) load_group(k0 + (g - 1) * PG, xn, Pn);
+      mean_rows(k0 + g * PG, g * PG, x);
+      R ov[PG][N], om[PG][N][N];
+#pragma unroll
+      for (int i = PG - 1; i >= 0; --i) {
+        const long k = k0 + g * PG + i;
+        if (k < T) sapply<N, P>(element(k, x[i], Pk[i]), st.v, st.m);
+        copy_vec<N, R>(st.v, ov[i]);
+        copy_mat<N, N, R>(st.m, om[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < PG; ++i) {
+        const long k = k0 + g * PG + i;
+        if (MLDS) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) ms[((g * PG + i) * N + r) * B] = ov[i][r];
+        }
+        if (k < T) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) {
+            if (!MLDS) mo[k * N + r] = ov[i][r];
+#pragma unroll
+            for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = om[i][r][c];
+          }
+        }
+      }
+    }
+    if (MLDS) {
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+        if (k0 + i < T) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) mo[(k0 + i) * N + r] = ms[(i * N + r) * B];
+        }
     }
   }
 };
@@ -884,8 +980,8 @@ template <int N, int M, class P, int BLOCK, int L>
 __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a,
                                                KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  RtsPipe<N, M, P, L> pp(a, io);
-  scan_tile<RtsPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+  RtsPipe<N, M, P, L, BLOCK> pp(a, io);
+  scan_tile<RtsPipe<N, M, P, L, BLOCK>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 // ---------------------------------------------------------------------------
