@@ -44,13 +44,14 @@ template <int N, int M, int L = 1> struct CL {
 // The preparation launch also zeroes the workspace's control region (tile
 // tickets, epochs, timeout flags, look-back status words and payloads) with a
 // grid-stride loop.  In block 0, wavefront 0 derives the generic element and
-// the aggregate tables while wavefront 1 derives the first element, so the two
-// serial FP64 chains overlap.
+// then the aggregate tables, each doubling step one Lemma 1 combine spread
+// over 16 lanes (mpart_combine_lanes), while wavefront 1 derives the first
+// element, so the FP64 chains overlap.
 //
 // Aggregate tables by doubling (L a power of two): with S_h the matrix part of
 // h consecutive generic elements and PHI_h[j], PSI_h[j] (j < h) its vector
 // coefficients, Lemma 1 for S_h (x) S_h (coefficients P1..P4, see
-// mpart_combine) gives
+// mpart_combine_lanes) gives
 //   j <  h:  PHI_2h[j] = P1 PHI_h[j],              PSI_2h[j] = PSI_h[j] - P4 PHI_h[j]
 //   j >= h:  PHI_2h[j] = P2 PSI_h[j-h] + PHI_h[j-h], PSI_2h[j] = P3 PSI_h[j-h]
 // starting from S_1 = (A, C, J), PHI_1[0] = K, PSI_1[0] = W.
@@ -67,10 +68,11 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   if (blockIdx.x != 0) return;
   using D = double;
   using LY = CL<N, M, L>;
-  __shared__ MPart<N, D> sS;          // S_h
+  __shared__ MPart<N, D> sS[2];       // S_h, double-buffered
   __shared__ D sPc[4][N][N];          // P1..P4 of S_h (x) S_h
-  __shared__ D sPHI[L][N][M], sPSI[L][N][M];
-  const int tid = threadIdx.x;
+  __shared__ D sW[4][N][N];           // combine scratch
+  __shared__ D sPHI[2][L][N][M], sPSI[2][L][N][M];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   auto load_model = [&](D (&F)[N][N], D (&Q)[N][N], D (&H)[M][N], D (&Rm)[M][M]) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -129,16 +131,16 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
         cst[LY::A + i * N + j] = R(A[i][j]);
         cst[LY::C + i * N + j] = R(Cs);
         cst[LY::J + i * N + j] = R(Jm[i][j]);
-        sS.A[i][j] = A[i][j];
-        sS.C[i][j] = Cs;
-        sS.J[i][j] = Jm[i][j];
+        sS[0].A[i][j] = A[i][j];
+        sS[0].C[i][j] = Cs;
+        sS[0].J[i][j] = Jm[i][j];
       }
 #pragma unroll
       for (int t = 0; t < M; ++t) {
         cst[LY::K + i * M + t] = R(Kt[t][i]);
         cst[LY::W + i * M + t] = R(Wt[t][i]);
-        sPHI[0][i][t] = Kt[t][i];
-        sPSI[0][i][t] = Wt[t][i];
+        sPHI[0][0][i][t] = Kt[t][i];
+        sPSI[0][0][i][t] = Wt[t][i];
       }
     }
   } else if (tid == WAVE) {
@@ -201,68 +203,61 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
       for (int j = 0; j < M; ++j) cst[LY::Rm + i * M + j] = R(0.5 * (Rm[i][j] + Rm[j][i]));
     }
   }
-  __syncthreads();
+  // doubling, all in wavefront 0 (lanes synchronise among themselves)
+  if (tid >= WAVE) return;
+  wave_lds_sync();
+  int cur = 0;
 #pragma unroll 1
   for (int h = 1; h < L; h *= 2) {
-    if (tid == 0) {
-      D P1[N][N], P2[N][N], P3[N][N], P4[N][N];
-      MPart<N, D> o;
-      mpart_combine<N, D>(sS, sS, o, P1, P2, P3, P4);
-      sS = o;
-      copy_mat<N, N, D>(P1, sPc[0]);
-      copy_mat<N, N, D>(P2, sPc[1]);
-      copy_mat<N, N, D>(P3, sPc[2]);
-      copy_mat<N, N, D>(P4, sPc[3]);
-    }
-    __syncthreads();
-    D nphi[N][M], npsi[N][M];
-    const int j = tid;
+    mpart_combine_lanes<N, D>(sS[cur], sS[cur], sS[cur ^ 1], sPc, sW, lane);
+    const int j = lane;
     if (j < 2 * h) {
+      D nphi[N][M], npsi[N][M];
       if (j < h) {
         D T1[N][M];
-        mm<N, N, M, D>(sPc[0], sPHI[j], nphi);
-        mm<N, N, M, D>(sPc[3], sPHI[j], T1);
+        mm<N, N, M, D>(sPc[0], sPHI[cur][j], nphi);
+        mm<N, N, M, D>(sPc[3], sPHI[cur][j], T1);
 #pragma unroll
         for (int r = 0; r < N; ++r)
 #pragma unroll
-          for (int c = 0; c < M; ++c) npsi[r][c] = sPSI[j][r][c] - T1[r][c];
+          for (int c = 0; c < M; ++c) npsi[r][c] = sPSI[cur][j][r][c] - T1[r][c];
       } else {
         D T1[N][M];
-        mm<N, N, M, D>(sPc[1], sPSI[j - h], T1);
+        mm<N, N, M, D>(sPc[1], sPSI[cur][j - h], T1);
 #pragma unroll
         for (int r = 0; r < N; ++r)
 #pragma unroll
-          for (int c = 0; c < M; ++c) nphi[r][c] = T1[r][c] + sPHI[j - h][r][c];
-        mm<N, N, M, D>(sPc[2], sPSI[j - h], npsi);
+          for (int c = 0; c < M; ++c) nphi[r][c] = T1[r][c] + sPHI[cur][j - h][r][c];
+        mm<N, N, M, D>(sPc[2], sPSI[cur][j - h], npsi);
       }
+      copy_mat<N, M, D>(nphi, sPHI[cur ^ 1][j]);
+      copy_mat<N, M, D>(npsi, sPSI[cur ^ 1][j]);
     }
-    __syncthreads();
-    if (j < 2 * h) {
-      copy_mat<N, M, D>(nphi, sPHI[j]);
-      copy_mat<N, M, D>(npsi, sPSI[j]);
-    }
-    __syncthreads();
+    wave_lds_sync();
+    cur ^= 1;
   }
-  if (tid < L) {
+  if (lane < L) {
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        cst[LY::PHI + tid * N * M + r * M + c] = R(sPHI[tid][r][c]);
-        cst[LY::PSI + tid * N * M + r * M + c] = R(sPSI[tid][r][c]);
+        cst[LY::PHI + lane * N * M + r * M + c] = R(sPHI[cur][lane][r][c]);
+        cst[LY::PSI + lane * N * M + r * M + c] = R(sPSI[cur][lane][r][c]);
       }
   }
-  if (tid == 0) {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        cst[LY::SL + i * N + j] = R(sS.A[i][j]);
-        cst[LY::SL + N * N + i * N + j] = R(sS.C[i][j]);
-        cst[LY::SL + 2 * N * N + i * N + j] = R(sS.J[i][j]);
-      }
+  if (lane < N * N) {
+    const int r = lane / N, c = lane % N;
+    cst[LY::SL + r * N + c] = R(sS[cur].A[r][c]);
+    cst[LY::SL + N * N + r * N + c] = R(sS[cur].C[r][c]);
+    cst[LY::SL + 2 * N * N + r * N + c] = R(sS[cur].J[r][c]);
   }
 }
+
+// Output stores are plain (write-back) stores: the L2 merges the 16-byte
+// pieces a thread writes for consecutive rows into whole lines before they
+// reach memory.  Non-temporal stores would send every piece to memory on its
+// own, which costs several times more.
+template <class R> KF_DEV void st_out(R* p, R v) { *p = v; }
 
 // Look-back state and sizes shared by the scans (array pointers travel as
 // separate kernel parameters, see IO below).  agg and pre hold tagged words
@@ -595,9 +590,9 @@ template <int N, int M, class P, int L> struct FilterPipe {
   KF_DEV void st_store_out(long k, const St<N, R>& st) const {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-      mo[k * N + r] = st.v[r];
+      st_out(&mo[k * N + r], st.v[r]);
 #pragma unroll
-      for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = st.m[r][c];
+      for (int c = 0; c < N; ++c) st_out(&Po[k * N * N + r * N + c], st.m[r][c]);
     }
   }
 };
@@ -734,7 +729,7 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
 #pragma unroll
             for (int r = 0; r < N; ++r)
 #pragma unroll
-              for (int cc = 0; cc < N; ++cc) Po[kj * N * N + r * N + cc] = om[j][r][cc];
+              for (int cc = 0; cc < N; ++cc) st_out(&Po[kj * N * N + r * N + cc], om[j][r][cc]);
         }
       }
       if (i % MG == MG - 1) {
@@ -743,7 +738,7 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
           const long kj = k - (MG - 1) + j;
           if (kj < T)
 #pragma unroll
-            for (int r = 0; r < N; ++r) mo[kj * N + r] = ov[j][r];
+            for (int r = 0; r < N; ++r) st_out(&mo[kj * N + r], ov[j][r]);
         }
       }
     }
@@ -879,6 +874,10 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
     }
   }
   KF_DEV E fold() {
+    E agg;
+    set_identity(agg);
+    R xn[PG][N], Pn[PG][N][N];
+    load_group(k0 + (NG - 1) * PG, xn, Pn);
     if (MLDS) {
       __shared__ R s_mean[MLDS ? L * N * B : 1];
       ms = s_mean + threadIdx.x;
@@ -887,10 +886,6 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
 #pragma unroll
         for (int r = 0; r < N; ++r) ms[(i * N + r) * B] = (k0 + i < T) ? mf[(k0 + i) * N + r] : R(0);
     }
-    E agg;
-    set_identity(agg);
-    R xn[PG][N], Pn[PG][N][N];
-    load_group(k0 + (NG - 1) * PG, xn, Pn);
 #pragma unroll 1
     for (int g = NG - 1; g >= 0; --g) {
       R x[PG][N], Pk[PG][N][N];
@@ -958,9 +953,9 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
         if (k < T) {
 #pragma unroll
           for (int r = 0; r < N; ++r) {
-            if (!MLDS) mo[k * N + r] = ov[i][r];
+            if (!MLDS) st_out(&mo[k * N + r], ov[i][r]);
 #pragma unroll
-            for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = om[i][r][c];
+            for (int c = 0; c < N; ++c) st_out(&Po[k * N * N + r * N + c], om[i][r][c]);
           }
         }
       }
@@ -970,7 +965,7 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
       for (int i = 0; i < L; ++i)
         if (k0 + i < T) {
 #pragma unroll
-          for (int r = 0; r < N; ++r) mo[(k0 + i) * N + r] = ms[(i * N + r) * B];
+          for (int r = 0; r < N; ++r) st_out(&mo[(k0 + i) * N + r], ms[(i * N + r) * B]);
         }
     }
   }
@@ -1075,9 +1070,9 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
       tf_combine<N, P>(xf, Pk, st.v, st.m, xs, Ps);
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        mo[k * N + r] = xs[r];
+        st_out(&mo[k * N + r], xs[r]);
 #pragma unroll
-        for (int c = 0; c < N; ++c) Po[k * N * N + r * N + c] = Ps[r][c];
+        for (int c = 0; c < N; ++c) st_out(&Po[k * N * N + r * N + c], Ps[r][c]);
       }
     }
   }

@@ -97,6 +97,31 @@ KF_DEV void lu_solve(const T (&LU)[N][N], const int (&piv)[N], const T (&dinv)[N
   }
 }
 
+// Solve M^T x = b in place from lu_factor's output (P M = L U, so
+// M^T = U^T L^T P): U^T w = b forward, L^T v = w backward, x = P^T v.
+template <int N, class T>
+KF_DEV void lu_solve_t(const T (&LU)[N][N], const int (&piv)[N], const T (&dinv)[N], T (&b)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int t = 0; t < i; ++t) b[i] -= LU[t][i] * b[t];
+    b[i] *= dinv[i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i)
+#pragma unroll
+    for (int t = i + 1; t < N; ++t) b[i] -= LU[t][i] * b[t];
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k)
+#pragma unroll
+    for (int r = k + 1; r < N; ++r) {
+      const bool s = (piv[k] == r);
+      const T a = b[k], c = b[r];
+      b[k] = s ? c : a;
+      b[r] = s ? a : c;
+    }
+}
+
 // In-place Cholesky of a symmetric positive-definite S = L L^T; the lower
 // triangle holds L, dinv[j] = 1 / L[j][j].
 template <int N, class T>

@@ -392,84 +392,96 @@ template <int N, class T> struct MPart {
   T J[N][N];
 };
 
+// Orders the LDS accesses of the lanes of one wavefront around this point.
+KF_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Coefficients of the vector part of Lemma 1 for left x (matrix part Sx) and
 // right y (matrix part Sy): with M = I + C_x J_y and Z = M^{-1} A_x,
 //   b = P1 b_x + P2 eta_y + b_y,   eta = P3 eta_y - P4 b_x + eta_x,
 //   P1 = A_y M^{-1}, P2 = P1 C_x, P3 = Z^T, P4 = Z^T J_y.
-// Also returns the matrix part of x (x) y.
+// The combine also gives the matrix part of x (x) y.
+// It is spread over the first N*N lanes of a wavefront, lane
+// l = r*N + c owning entry (r, c) of every result; every lane of the
+// wavefront must call it (it synchronises the wavefront between phases).
+// x, y, o, the coefficients Pc = {P1, P2, P3, P4} and the scratch W live in
+// LDS; o must not alias x or y.  Each lane factorises M = I + C_x J_y itself
+// and solves for column c of Z = M^{-1} A_x and Y = M^{-1} C_x and for row r
+// of P1 = A_y M^{-1}; the products then take one dot product per lane.
+// Symmetric results are formed from the upper triangle in both lanes (r, c)
+// and (c, r), so they are exactly symmetric.
 template <int N, class T>
-KF_DEV void mpart_combine(const MPart<N, T>& x, const MPart<N, T>& y, MPart<N, T>& o,
-                          T (&P1)[N][N], T (&P2)[N][N], T (&P3)[N][N], T (&P4)[N][N]) {
-  T M[N][N];
-  mm<N, N, N, T>(x.C, y.J, M);
+KF_DEV void mpart_combine_lanes(const MPart<N, T>& x, const MPart<N, T>& y, MPart<N, T>& o,
+                                T (&Pc)[4][N][N], T (&W)[4][N][N], int lane) {
+  const bool on = lane < N * N;
+  const int r = on ? lane / N : 0, c = on ? lane % N : 0;
+  const int i = r < c ? r : c, j = r < c ? c : r;
+  if (on) {
+    T m = (r == c) ? T(1) : T(0);
 #pragma unroll
-  for (int i = 0; i < N; ++i) M[i][i] += T(1);
-  int piv[N];
-  T dinv[N];
-  lu_factor<N, T>(M, piv, dinv);
-  // Z = M^{-1} A_x, Y = M^{-1} C_x, and M^{-T} A_y^T = P1^T
-  T B[N][2 * N];
-#pragma unroll
-  for (int r = 0; r < N; ++r)
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      B[r][c] = x.A[r][c];
-      B[r][N + c] = x.C[r][c];
-    }
-  // P1 = A_y M^{-1}  <=>  P1^T = M^{-T} A_y^T: solve with the transposed
-  // factorisation (U^T then L^T, then undo the row interchanges)
-  T Pt[N][N];
-#pragma unroll
-  for (int r = 0; r < N; ++r)
-#pragma unroll
-    for (int c = 0; c < N; ++c) Pt[r][c] = y.A[c][r];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int t = 0; t < i; ++t)
-#pragma unroll
-      for (int c = 0; c < N; ++c) Pt[i][c] -= M[t][i] * Pt[t][c];
-#pragma unroll
-    for (int c = 0; c < N; ++c) Pt[i][c] *= dinv[i];
+    for (int t = 0; t < N; ++t) m += x.C[r][t] * y.J[t][c];
+    W[0][r][c] = m;
   }
+  wave_lds_sync();
+  if (on) {
+    T M[N][N], dinv[N], zc[N][1], yc[N][1], p1[N];
+    int piv[N];
 #pragma unroll
-  for (int i = N - 1; i >= 0; --i)
+    for (int a = 0; a < N; ++a) {
 #pragma unroll
-    for (int t = i + 1; t < N; ++t)
-#pragma unroll
-      for (int c = 0; c < N; ++c) Pt[i][c] -= M[t][i] * Pt[t][c];
-#pragma unroll
-  for (int k = N - 1; k >= 0; --k)
-#pragma unroll
-    for (int r = k + 1; r < N; ++r) {
-      bool s = (piv[k] == r);
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        T a = Pt[k][c], b = Pt[r][c];
-        Pt[k][c] = s ? b : a;
-        Pt[r][c] = s ? a : b;
-      }
+      for (int b = 0; b < N; ++b) M[a][b] = W[0][a][b];
+      zc[a][0] = x.A[a][c];
+      yc[a][0] = x.C[a][c];
+      p1[a] = y.A[r][a];
     }
-  lu_solve<N, 2 * N, T>(M, piv, dinv, B);
-  T Z[N][N], Y[N][N];
+    lu_factor<N, T>(M, piv, dinv);
+    lu_solve<N, 1, T>(M, piv, dinv, zc);
+    lu_solve<N, 1, T>(M, piv, dinv, yc);
+    lu_solve_t<N, T>(M, piv, dinv, p1);
+    T zr = zc[0][0], yr = yc[0][0], pr = p1[0];
 #pragma unroll
-  for (int r = 0; r < N; ++r)
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      Z[r][c] = B[r][c];
-      Y[r][c] = B[r][N + c];
-      P1[r][c] = Pt[c][r];
-      P3[c][r] = B[r][c];  // Z^T
+    for (int a = 1; a < N; ++a) {
+      zr = (a == r) ? zc[a][0] : zr;
+      yr = (a == r) ? yc[a][0] : yr;
+      pr = (a == c) ? p1[a] : pr;
     }
-  mm<N, N, N, T>(P1, x.C, P2);
-  mm<N, N, N, T>(P3, y.J, P4);
-  mm<N, N, N, T>(y.A, Z, o.A);
-  T AY[N][N];
-  mm<N, N, N, T>(y.A, Y, AY);
-  sym_xyt_plus<N, N, T>(AY, y.A, y.C, o.C);
-  T JA[N][N];
-  mm<N, N, N, T>(y.J, x.A, JA);
-  sym_xty_plus<N, N, T>(Z, JA, x.J, o.J);
+    W[1][r][c] = zr;  // Z
+    W[2][r][c] = yr;  // Y
+    Pc[0][r][c] = pr;
+  }
+  wave_lds_sync();
+  if (on) {
+    T p2 = T(0), p4 = T(0), oa = T(0), ay = T(0), ja = T(0);
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      p2 += Pc[0][r][t] * x.C[t][c];
+      p4 += W[1][t][r] * y.J[t][c];
+      oa += y.A[r][t] * W[1][t][c];
+      ay += y.A[r][t] * W[2][t][c];
+      ja += y.J[r][t] * x.A[t][c];
+    }
+    Pc[1][r][c] = p2;
+    Pc[2][r][c] = W[1][c][r];
+    Pc[3][r][c] = p4;
+    o.A[r][c] = oa;
+    W[0][r][c] = ay;  // A_y Y
+    W[3][r][c] = ja;  // J_y A_x
+  }
+  wave_lds_sync();
+  if (on) {
+    T oc = y.C[i][j], oj = x.J[i][j];
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      oc += W[0][i][t] * y.A[j][t];
+      oj += W[1][t][i] * W[3][t][j];
+    }
+    o.C[r][c] = oc;
+    o.J[r][c] = oj;
+  }
+  wave_lds_sync();
 }
 
 // One Kalman predict/update step (Sec. III-A) applied to an anchored state
