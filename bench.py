@@ -8,8 +8,11 @@ already resident in HBM.  `value` is time steps (measurements) processed per
 second: T * K / wall time of K passes.
 
 Each pass is enqueued stage by stage (kf_prepare, kf_pass_filter,
-kf_pass_rts) with HIP events between the stages on the launch stream, so the
-per-kernel durations used for the roofline come from the timed region itself.
+kf_pass_rts) on the launch stream.  Every --event-every-th pass of the timed
+region also records HIP events between its stages; those sampled passes give
+the per-kernel durations used for the roofline and the per-pass latency
+percentiles.  (An event between stages costs about 5 us of idle GPU time, so
+they are not put into every pass.)
 The CPU baseline times the FP64 sequential oracle (filter + RTS) on this
 machine's host, one core, on the same input.
 
@@ -60,8 +63,10 @@ def load_traffic(kernel: str, workload: str, precision: str):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--event-every", type=int, default=4,
+                    help="record stage events on every n-th timed pass")
     ap.add_argument("--precision", default="f32", choices=["f32", "mixed", "f64"])
     ap.add_argument("--log2T", type=int, default=20)
     ap.add_argument("--scan", default="lookback",
@@ -114,13 +119,16 @@ def main() -> int:
     torch.cuda.synchronize()
 
     K = args.steps
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    every = max(1, args.event_every)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] if i % every == 0 else None
+              for i in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
         one_pass(events[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    events = [e for e in events if e is not None]
 
     # device-copy reference: 256 MiB through the library's plain copy kernel,
     # timed with events (also the calibration dispatch of the counter runs)
