@@ -139,3 +139,32 @@ def test_eta1_J1_do_not_matter():
     b = scans.sequential(el2, oracle.filter_combine, ident)
     for s1, s2 in zip(a, b):
         assert np.array_equal(s1[1], s2[1]) and np.array_equal(s1[2], s2[2])
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_zero_decay_element_is_an_anchor(n):
+    """Lemmas 1 and 2: an element whose decay matrix (A, resp. E) is exactly
+    zero fixes the anchored part of every product it takes part in -- (b, C) of
+    p (x) x and (eta, J) of x (x) q for filtering elements, (g, L) of x (x) q for
+    smoothing elements -- whatever the other operand.  The first filtering
+    element (A_1 = 0, eq. pkf_init2) and the last smoothing element (E_T = 0,
+    eq. prts_init2) are such anchors; the GPU look-back also stops at any
+    aggregate whose decay matrix has underflowed to zero."""
+    rng = np.random.default_rng(70 + n)
+    for _ in range(4):
+        p, q, x = (_random_filter_element(rng, n) for _ in range(3))
+        x = (np.zeros((n, n)),) + tuple(x[1:])
+        r = oracle.filter_combine(p, x)
+        assert np.array_equal(r[1], x[1]) and np.array_equal(r[2], x[2])
+        r = oracle.filter_combine(x, q)
+        assert np.array_equal(r[3], x[3]) and np.array_equal(r[4], x[4])
+        # the product keeps a zero decay matrix (it stays an anchor)
+        assert np.array_equal(oracle.filter_combine(p, x)[0], np.zeros((n, n)))
+    F, Q, H, R, m0, P0, u, d = _rand_model(rng, n, 1, tv=False, T=6, inputs=False)
+    y = rng.standard_normal((6, 1))
+    m_f, P_f, _, _ = oracle.kf_filter(F, Q, H, R, m0, P0, y)
+    el = oracle.smooth_elements(F, Q, m_f, P_f)
+    for k in range(5):
+        xs = (np.zeros((n, n)),) + tuple(el[k][1:])
+        r = oracle.smooth_combine(xs, el[k + 1])
+        assert np.array_equal(r[1], xs[1]) and np.array_equal(r[2], xs[2])
