@@ -16,6 +16,12 @@ they are not put into every pass.)
 The CPU baseline times the FP64 sequential oracle (filter + RTS) on this
 machine's host, one core, on the same input.
 
+Other single-GPU workloads of the same model: --T / --log2T set the length
+(T = 1000 and T = 2^18 are the small-case and two-filter configurations),
+--smoother tf times the two-filter smoother (Algorithm 7) instead of the RTS
+pass, --precision selects f32, mixed (FP32 storage, FP64 solves) or f64, and
+--scan selects the scan (look-back, or the one-kernel-per-level tree scans).
+
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -69,6 +75,9 @@ def main() -> int:
                     help="record stage events on every n-th timed pass")
     ap.add_argument("--precision", default="f32", choices=["f32", "mixed", "f64"])
     ap.add_argument("--log2T", type=int, default=20)
+    ap.add_argument("--T", type=int, default=0, help="sequence length (overrides --log2T)")
+    ap.add_argument("--smoother", default="rts", choices=["rts", "tf"],
+                    help="RTS (Algorithm 6) or two-filter (Algorithm 7) backward pass")
     ap.add_argument("--scan", default="lookback",
                     choices=["lookback", "lookback_generic", "blelloch", "hillis_steele"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -90,8 +99,11 @@ def main() -> int:
     kfscan.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    T = 1 << args.log2T
+    T = args.T if args.T > 0 else 1 << args.log2T
+    tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
+    back = "kf_pass_rts" if args.smoother == "rts" else "kf_pass_twofilter"
+    kback = "k_rts" if args.smoother == "rts" else "k_twofilter"
     n, m = 4, 2
     w = 8 if prec == "f64" else 4
 
@@ -110,7 +122,7 @@ def main() -> int:
         plan("kf_pass_filter")
         if evs is not None:
             evs[2].record()
-        plan("kf_pass_rts")
+        plan(back)
         if evs is not None:
             evs[3].record()
 
@@ -151,19 +163,19 @@ def main() -> int:
     lat = np.array([e[0].elapsed_time(e[3]) for e in events])          # ms per whole pass
     t_prep = np.array([e[0].elapsed_time(e[1]) for e in events])
     t_filt = np.array([e[1].elapsed_time(e[2]) for e in events])
-    t_rts = np.array([e[2].elapsed_time(e[3]) for e in events])
+    t_back = np.array([e[2].elapsed_time(e[3]) for e in events])
 
     # algorithmic bytes per launch: forward pass reads y and writes the filter
-    # moments, the RTS pass writes the smoothed moments; their sum is the
+    # moments, the backward pass writes the smoothed moments; their sum is the
     # job's compulsory traffic w (m + 2n + 2n^2) per step
     bytes_filter = T * w * (m + n + n * n)
-    bytes_rts = T * w * (n + n * n)
+    bytes_back = T * w * (n + n * n)
     kern = {"k_filter": (float(t_filt.mean()), bytes_filter),
-            "k_rts": (float(t_rts.mean()), bytes_rts)}
+            kback: (float(t_back.mean()), bytes_back)}
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_bytes = kern[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, "tracking_T2^%d_%s" % (args.log2T, args.scan), prec)
+    traffic = load_traffic(dom, "tracking_%s_%s" % (tname, args.scan), prec)
 
     # accuracy of this run against the FP64 oracle, and the CPU baseline
     m_f, P_f, m_s, P_s = (t[0].double().cpu().numpy() for t in plan.outputs())
@@ -179,15 +191,17 @@ def main() -> int:
             yy = cast(y_np)
         reps = 0
         c0 = time.perf_counter()
+        smooth = oracle.smooth_rts if args.smoother == "rts" else oracle.smooth_twofilter
         while True:
-            ref = oracle.smooth_rts(*arrs, yy)
+            ref = smooth(*arrs, yy)
             reps += 1
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
         c1 = time.perf_counter()
         cpu = {"value": T * reps / (c1 - c0), "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": "sequential FP64 filter + RTS smoother over the full T=2^%d input, "
-                         "%d repetition(s)" % (args.log2T, reps)}
+               "sample": "sequential FP64 filter + %s smoother over the full T=%d input, "
+                         "%d repetition(s)" % ({"rts": "RTS", "tf": "two-filter"}[args.smoother],
+                                               T, reps)}
 
         def nw(a, r):
             return float(np.max(np.abs(a - r)) / max(np.max(np.abs(r)), 1e-300))
@@ -209,16 +223,16 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": "cv_tracking_nx4_ny2_T2^%d" % args.log2T, "T": T, "nx": n, "ny": m,
+        "config": {"workload": "cv_tracking_nx4_ny2_%s" % tname, "T": T, "nx": n, "ny": m,
                    "dt": 0.1, "q": 1.0, "r": 0.25, "sequences": 1,
-                   "pipeline": "kf_prepare+kf_pass_filter+kf_pass_rts",
+                   "pipeline": "kf_prepare+kf_pass_filter+" + back,
                    "scan": args.scan, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "kernel_ms": {"k_prepare": float(t_prep.mean()), "k_filter": float(t_filt.mean()),
-                      "k_rts": float(t_rts.mean())},
+                      kback: float(t_back.mean())},
         "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
         "copy_GBps": copy_gbps,
         "errors_vs_oracle": errors,

@@ -43,7 +43,9 @@ static kf_status check_sizes(const kf_problem* p) {
   // the tree scans put sequences on the grid's y dimension
   if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
   const Layout L = make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
-  if ((double)L.max_tiles * (double)p->nseq > 2147483647.0) return KF_ERR_INVALID_ARG;
+  if ((double)L.ntiles[0] * (double)p->nseq > 2147483647.0 ||
+      (double)L.ntiles[1] * (double)p->nseq > 2147483647.0)
+    return KF_ERR_INVALID_ARG;
   return KF_OK;
 }
 

@@ -5,7 +5,24 @@
 #include "kf_tree.hpp"
 #include "kf_plan.hpp"
 
+#include <type_traits>
+
 namespace kfs {
+
+// Calls fn(std::integral_constant<int, L>{}) for the runtime L in {2, 4, 8,
+// 16}, instantiating only the values up to LMAX.
+template <int LMAX, class Fn> void with_items(int L, Fn&& fn) {
+  if constexpr (LMAX >= 16) {
+    if (L == 16) return fn(std::integral_constant<int, 16>{});
+  }
+  if constexpr (LMAX >= 8) {
+    if (L == 8) return fn(std::integral_constant<int, 8>{});
+  }
+  if constexpr (LMAX >= 4) {
+    if (L == 4) return fn(std::integral_constant<int, 4>{});
+  }
+  fn(std::integral_constant<int, 2>{});
+}
 
 template <int N, int M, class P>
 kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
@@ -16,12 +33,18 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
   constexpr int ITI = items_ti(N);
   R* cst = reinterpret_cast<R*>(ws + L.cst);
   const size_t prep_blocks = (L.ctrl_words + 255) / 256;
+  const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
+  // the aggregate tables are built for the forward scan's L (unused by the
+  // generic scan, whose L only sizes them)
   if (stages & ST_PREPARE)
-    hipLaunchKernelGGL((k_prepare<N, M, R, ITI>), dim3(prep_blocks < 1024 ? prep_blocks : 1024),
-                       dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
-                       static_cast<const R*>(p.H), static_cast<const R*>(p.R),
-                       static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
-                       reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+    with_items<ITI>(L.items[0], [&](auto c) {
+      hipLaunchKernelGGL((k_prepare<N, M, R, decltype(c)::value>),
+                         dim3(prep_blocks < 1024 ? prep_blocks : 1024), dim3(256), 0, st,
+                         static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                         static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                         static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
+                         reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+    });
   const R* y = static_cast<const R*>(p.y);
   R* mf = static_cast<R*>(p.m_filt);
   R* Pf = static_cast<R*>(p.P_filt);
@@ -41,37 +64,43 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
     }
     return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
   }
-  const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
-  auto args = [&](int slot, int items) {
+  auto args = [&](int slot) {
     ScanArgs<R> a{};
     a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
     a.agg = reinterpret_cast<u64*>(ws + L.agg[slot]);
     a.pre = reinterpret_cast<u64*>(ws + L.pre[slot]);
     a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
     a.T = p.T;
-    a.ntiles = ntiles_for(p.T, items);
+    a.ntiles = L.ntiles[slot];
     a.nseq = p.nseq;
     a.lb_group = lookback_group(a.ntiles);
     return a;
   };
   auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
   if (stages & ST_FORWARD) {
-    ScanArgs<R> fa = args(0, generic ? IT : ITI);
+    ScanArgs<R> fa = args(0);
     if (generic)
-      hipLaunchKernelGGL((k_filter<N, M, P, B, IT>), grid(fa), dim3(B), 0, st, fa, cst, y,
-                         (const R*)nullptr, (const R*)nullptr, mf, Pf);
+      with_items<IT>(L.items[0], [&](auto c) {
+        hipLaunchKernelGGL((k_filter<N, M, P, B, decltype(c)::value>), grid(fa), dim3(B), 0, st,
+                           fa, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
+      });
     else
-      hipLaunchKernelGGL((k_filter_ti<N, M, P, B, ITI>), grid(fa), dim3(B), 0, st, fa, cst, y,
-                         (const R*)nullptr, (const R*)nullptr, mf, Pf);
+      with_items<ITI>(L.items[0], [&](auto c) {
+        hipLaunchKernelGGL((k_filter_ti<N, M, P, B, decltype(c)::value>), grid(fa), dim3(B), 0,
+                           st, fa, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
+      });
   }
   if (op != OP_FILTER && (stages & ST_BACKWARD)) {
-    ScanArgs<R> ba = args(1, IT);
-    if (op == OP_RTS)
-      hipLaunchKernelGGL((k_rts<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba, cst, y,
-                         (const R*)mf, (const R*)Pf, ms, Ps);
-    else
-      hipLaunchKernelGGL((k_twofilter<N, M, P, B, IT>), grid(ba), dim3(B), 0, st, ba, cst, y,
-                         (const R*)mf, (const R*)Pf, ms, Ps);
+    ScanArgs<R> ba = args(1);
+    with_items<IT>(L.items[1], [&](auto c) {
+      constexpr int IL = decltype(c)::value;
+      if (op == OP_RTS)
+        hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(ba), dim3(B), 0, st, ba, cst, y,
+                           (const R*)mf, (const R*)Pf, ms, Ps);
+      else
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL>), grid(ba), dim3(B), 0, st, ba, cst, y,
+                           (const R*)mf, (const R*)Pf, ms, Ps);
+    });
   }
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }
@@ -86,6 +115,22 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
   X(4, 1)             \
   X(4, 2)             \
   X(4, 4)
+
+// Each shape's launches are instantiated in a translation unit of their own
+// (kf_inst_<precision>_<group>.hip), so the library compiles in parallel.
+#define KFS_EXTERN(n, m)                                                                   \
+  extern template kf_status run_shape<n, m, PrecF64>(Op, int, const kf_problem&, char*,    \
+                                                     const Layout&, hipStream_t);          \
+  extern template kf_status run_shape<n, m, PrecF32>(Op, int, const kf_problem&, char*,    \
+                                                     const Layout&, hipStream_t);          \
+  extern template kf_status run_shape<n, m, PrecMixed>(Op, int, const kf_problem&, char*,  \
+                                                       const Layout&, hipStream_t);
+KFS_SHAPES(KFS_EXTERN)
+#undef KFS_EXTERN
+
+#define KFS_INSTANTIATE(n, m, P)                                                           \
+  template kf_status run_shape<n, m, P>(Op, int, const kf_problem&, char*, const Layout&,  \
+                                        hipStream_t);
 
 template <class P>
 kf_status run_prec(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,

@@ -1,4 +1,4 @@
-// Kernel instantiations for precision policy PrecF32.
+// Shape dispatch for precision policy PrecF32.
 #include "kf_inst.hpp"
 
 namespace kfs {

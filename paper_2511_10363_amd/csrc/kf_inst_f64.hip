@@ -1,4 +1,4 @@
-// Kernel instantiations for precision policy PrecF64.
+// Shape dispatch for precision policy PrecF64.
 #include "kf_inst.hpp"
 
 namespace kfs {

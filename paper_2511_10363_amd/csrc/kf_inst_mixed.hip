@@ -1,4 +1,4 @@
-// Kernel instantiations for precision policy PrecMixed.
+// Shape dispatch for precision policy PrecMixed.
 #include "kf_inst.hpp"
 
 namespace kfs {

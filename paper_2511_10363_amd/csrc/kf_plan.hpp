@@ -11,13 +11,29 @@ namespace kfs {
 
 constexpr int kBlock = 256;
 
-// Time steps each thread owns: in the scans over full elements, and in the
-// time-invariant scans whose per-thread fold is a linear map of the
-// measurements (so a thread can own more steps).
+// Time steps each thread owns (L), at most: in the scans over full elements,
+// and in the time-invariant filter, whose per-thread fold is a linear map of
+// the measurements (so a thread can own more steps).  The launch takes the
+// largest power of two L <= the maximum (and >= 2) that still gives a target
+// number of tiles.  The time-invariant filter aims at 256 tiles, one per CU,
+// since its fold is cheap and its wavefront totals become anchors early.  The
+// full-element scans keep the longest tiles unless a sequence would have fewer
+// than 4: their tile aggregates must be long to underflow into anchors (see
+// decay_is_zero), and a short-tile look-back over non-anchored aggregates
+// costs more than the parallelism gained.
 constexpr int items_per_thread(int nx) { return nx <= 2 ? 16 : (nx <= 4 ? 8 : 4); }
 constexpr int items_ti(int nx) { return nx <= 4 ? 16 : 8; }
-constexpr int items_min(int nx) {
-  return items_per_thread(nx) < items_ti(nx) ? items_per_thread(nx) : items_ti(nx);
+constexpr long kTilesTi = 256, kTilesScan = 4;
+
+inline long ntiles_for(long T, int items) {
+  const long tile = (long)kBlock * items;
+  return (T + tile - 1) / tile;
+}
+
+inline int choose_items(long T, long nseq, int lmax, long target) {
+  int L = lmax;
+  while (L > 2 && nseq * ntiles_for(T, L) < target) L /= 2;
+  return L;
 }
 
 inline size_t word_bytes(int precision) { return precision == KF_PREC_F64 ? 8 : 4; }
@@ -38,7 +54,8 @@ struct Layout {
   size_t cst;                 // derived model quantities
   size_t tree[2];             // element buffers of the tree scans (Hillis-Steele: both)
   long tree_positions;        // scan positions per sequence of the tree scans
-  long max_tiles;             // tiles per sequence at the smallest tile size
+  int items[2];               // steps per thread of the forward and backward scans
+  long ntiles[2];             // tiles per sequence of the forward and backward scans
   size_t total;
 };
 
@@ -47,11 +64,6 @@ struct Layout {
 inline int lookback_group(long ntiles) {
   const long g = (ntiles + kBlock - 1) / kBlock;
   return (int)(g < 1 ? 1 : (g > 4 ? 4 : g));
-}
-
-inline long ntiles_for(long T, int items) {
-  const long tile = (long)kBlock * items;
-  return (T + tile - 1) / tile;
 }
 
 inline bool is_tree_scan(int scan) {
@@ -70,8 +82,13 @@ inline Layout make_layout(int nx, int ny, int precision, int scan, long T, long 
   const size_t halves = w / 4;                           // tagged words per scalar
   const long n = nx, m = ny;
   Layout L{};
-  L.max_tiles = ntiles_for(T, items_min(nx));
-  const size_t nt = (size_t)L.max_tiles * (size_t)nseq;
+  L.items[0] = (scan == KF_SCAN_LOOKBACK_GENERIC)
+                   ? choose_items(T, nseq, items_per_thread(nx), kTilesScan)
+                   : choose_items(T, nseq, items_ti(nx), kTilesTi);
+  L.items[1] = choose_items(T, nseq, items_per_thread(nx), kTilesScan);
+  L.ntiles[0] = ntiles_for(T, L.items[0]);
+  L.ntiles[1] = ntiles_for(T, L.items[1]);
+  const size_t ntf[2] = {(size_t)L.ntiles[0] * (size_t)nseq, (size_t)L.ntiles[1] * (size_t)nseq};
   const size_t cst_words =                               // CL<N, M, L>::SIZE
       10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(nx) * n * m;
   const size_t elem_words = 3 * n * n + 2 * n;           // largest element (filtering)
@@ -83,14 +100,14 @@ inline Layout make_layout(int nx, int ny, int precision, int scan, long T, long 
   }
   for (int s = 0; s < 2; ++s) {
     L.flags[s] = off;
-    off += nt * sizeof(int);
+    off += ntf[s] * sizeof(int);
   }
   off = (off + 7) & ~size_t(7);
   for (int s = 0; s < 2; ++s) {
     L.agg[s] = off;
-    off += nt * elem_words * halves * 8;
+    off += ntf[s] * elem_words * halves * 8;
     L.pre[s] = off;
-    off += nt * pre_words * halves * 8;
+    off += ntf[s] * pre_words * halves * 8;
   }
   L.ctrl_words = off / 4;
   off = align256(off);

@@ -75,12 +75,14 @@ def test_tracking_T1000(entry, prec, scan):
 
 
 @pytest.mark.parametrize("scan", ALL_KINDS)
-@pytest.mark.parametrize("T", [1, 2, 3, 7, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096,
-                               4097, 6000, 8193, 12289])
+@pytest.mark.parametrize("T", [1, 2, 3, 7, 63, 64, 65, 511, 512, 513, 1000, 1023, 1024, 1025,
+                               1500, 2047, 2048, 2049, 4095, 4096, 4097, 6000, 8193, 12289])
 @pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
 def test_ragged_lengths_f64(entry, T, scan):
-    """Empty-tail tiles, single steps and tile boundaries (2048 steps per tile
-    for the full-element scans, 4096 for the time-invariant one at nx=4)."""
+    """Empty-tail tiles, single steps and tile boundaries.  A tile is 256 * L
+    steps: the time-invariant filter takes L = 2 (512-step tiles) at all these
+    lengths; the full-element scans take the longest L that still gives 4
+    tiles: L = 2 up to 2048 steps, 4 up to 8192, then 8 (2048-step tiles)."""
     model, y = W.tracking(T, seed=T)
     _check(entry, model, y, "f64", scan=scan)
 
@@ -145,6 +147,18 @@ def test_full_size_tree_scans_T_2_20(prec, scan):
     model, y = W.tracking(T, seed=20251110)
     errs = _check("rts", model, y, prec, scan=scan)
     _say("errors", errs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("entry", ["rts", "tf"])
+def test_intermediate_tile_sizes(entry, prec):
+    """T = 2^19 + 12345 selects L = 8 for the time-invariant filter (2^20 selects
+    16, 2^18 selects 4, short sequences 2), so with the ragged-length and
+    full-size tests every compiled L of the nx = 4 kernels is compared with the
+    oracle."""
+    T = (1 << 19) + 12345
+    model, y = W.tracking(T, seed=19)
+    _check(entry, model, y, prec)
 
 
 def test_full_size_twofilter_T_2_18():
