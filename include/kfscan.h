@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define KFSCAN_ABI_VERSION 1
+#define KFSCAN_ABI_VERSION 2
 
 typedef enum kf_status {
     KF_OK = 0,
@@ -104,6 +104,28 @@ typedef struct kf_problem {
     void *m_smooth, *P_smooth;             /* smoother outputs, device (smoothers)  */
 } kf_problem;
 
+/* A batch of independent sequences of different lengths (Sec. IV applies to
+ * each one separately), packed into shared arrays, with one model for all or
+ * one model per sequence:
+ *   sequence i has T[i] steps; its measurements are rows offset[i] ..
+ *   offset[i] + T[i] - 1 of y, and its results the same rows of the outputs.
+ * All sequences share nx and ny. */
+typedef struct kf_batch {
+    int32_t nx;            /* state dimension n                                   */
+    int32_t ny;            /* measurement dimension m                             */
+    int32_t precision;     /* kf_precision                                        */
+    int32_t scan;          /* KF_SCAN_AUTO, KF_SCAN_LOOKBACK or _LOOKBACK_GENERIC */
+    int64_t nseq;          /* number of sequences, 1 .. 2^22                      */
+    int64_t nmodels;       /* 1 (shared model) or nseq (model i for sequence i)   */
+    int64_t total_steps;   /* rows of y and of the outputs, >= sum of T[i]        */
+    const int64_t *T;      /* device [nseq], T[i] >= 1                            */
+    const int64_t *offset; /* device [nseq], 0 <= offset[i] <= total_steps - T[i] */
+    const void *F, *Q, *H, *R, *m0, *P0;  /* device, [nmodels] models back to back  */
+    const void *y;                         /* device [total_steps][ny]               */
+    void *m_filt, *P_filt;                 /* device [total_steps][nx], [..][nx][nx] */
+    void *m_smooth, *P_smooth;             /* device, smoothers only                 */
+} kf_batch;
+
 /* ABI version (KFSCAN_ABI_VERSION). */
 int kf_abi_version(void);
 
@@ -128,6 +150,16 @@ kf_status kf_workspace_clear(void *workspace, size_t bytes, void *stream);
  * for calibrating hardware traffic counters.  Asynchronous on `stream`. */
 kf_status kf_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Diagnostic, synchronises `stream`: the error bits of the last call that
+ * used this workspace, or-ed over its scans: bit 0, a look-back wait gave up
+ * (see kf_workspace_timed_out); bit 1, a ragged batch held a sequence with
+ * T[i] < 1 or rows outside [0, total_steps), or lengths adding up to more
+ * than total_steps.  Such sequences (all of them in the last case) are skipped:
+ * no kernel reads or writes their rows, and their outputs are left as they
+ * were.  Needs at least the first 32 bytes of the workspace. */
+kf_status kf_workspace_status(const void *workspace, size_t workspace_bytes, uint32_t *status,
+                              void *stream);
+
 /* Diagnostic, synchronises `stream`: sets *timed_out to 1 if a look-back wait
  * in the last call that used this workspace gave up (a predecessor tile
  * never published within about a second, so that call's outputs are
@@ -145,6 +177,21 @@ kf_status kf_smooth_rts(const kf_problem *p, void *workspace, size_t workspace_b
 /* Algorithm 7: writes m_filt, P_filt (the forward pass) and m_smooth, P_smooth. */
 kf_status kf_smooth_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
                               void *stream);
+
+/* ---- Ragged batches ----------------------------------------------------
+ * The same three computations over a kf_batch.  The device arrays T and offset
+ * are checked on the device (kf_workspace_status); everything else on the
+ * host.  The tiling is chosen from the mean length total_steps / nseq.  The
+ * one-kernel-per-level scans are not offered for batches
+ * (KF_ERR_UNSUPPORTED).  Sequences whose output rows overlap give undefined
+ * results in the overlap. */
+kf_status kf_batch_workspace_size(const kf_batch *b, size_t *bytes);
+kf_status kf_filter_batch(const kf_batch *b, void *workspace, size_t workspace_bytes,
+                          void *stream);
+kf_status kf_smooth_rts_batch(const kf_batch *b, void *workspace, size_t workspace_bytes,
+                              void *stream);
+kf_status kf_smooth_twofilter_batch(const kf_batch *b, void *workspace, size_t workspace_bytes,
+                                    void *stream);
 
 /* ---- Stage entry points ------------------------------------------------
  * For callers that schedule or time the passes themselves.  Each enqueues

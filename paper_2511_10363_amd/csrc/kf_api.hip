@@ -32,43 +32,90 @@ bool shape_built(int nx, int ny) {
   return false;
 }
 
+static kf_status check_common(int nx, int ny, int precision, int scan) {
+  if (nx < 1 || ny < 1) return KF_ERR_INVALID_ARG;
+  if (precision < KF_PREC_F64 || precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
+  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_LOOKBACK_GENERIC) return KF_ERR_INVALID_ARG;
+  if (!shape_built(nx, ny)) return KF_ERR_UNSUPPORTED;
+  return KF_OK;
+}
+
+static kf_status check_layout(const Job& j) {
+  const Layout L = make_layout(j);
+  if (L.grid[0] > 2147483647L || L.grid[1] > 2147483647L) return KF_ERR_INVALID_ARG;
+  return KF_OK;
+}
+
 static kf_status check_sizes(const kf_problem* p) {
   if (!p) return KF_ERR_INVALID_ARG;
-  if (p->nx < 1 || p->ny < 1 || p->T < 1 || p->nseq < 1) return KF_ERR_INVALID_ARG;
-  if (p->precision < KF_PREC_F64 || p->precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
-  if (p->scan < KF_SCAN_AUTO || p->scan > KF_SCAN_LOOKBACK_GENERIC) return KF_ERR_INVALID_ARG;
+  if (p->T < 1 || p->nseq < 1) return KF_ERR_INVALID_ARG;
   // tile counts and element offsets stay well inside 32-bit grid limits
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
-  if (!shape_built(p->nx, p->ny)) return KF_ERR_UNSUPPORTED;
+  kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
+  if (s != KF_OK) return s;
   // the tree scans put sequences on the grid's y dimension
   if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
-  const Layout L = make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
-  if ((double)L.ntiles[0] * (double)p->nseq > 2147483647.0 ||
-      (double)L.ntiles[1] * (double)p->nseq > 2147483647.0)
+  return check_layout(job_of(*p));
+}
+
+static kf_status check_batch(const kf_batch* b) {
+  if (!b) return KF_ERR_INVALID_ARG;
+  if (b->nseq < 1 || b->nseq > (int64_t(1) << 22)) return KF_ERR_INVALID_ARG;
+  if (b->nmodels != 1 && b->nmodels != b->nseq) return KF_ERR_INVALID_ARG;
+  if (b->total_steps < 1 || b->total_steps > (int64_t(1) << 40)) return KF_ERR_INVALID_ARG;
+  kf_status s = check_common(b->nx, b->ny, b->precision, b->scan);
+  if (s != KF_OK) return s;
+  if (is_tree_scan(b->scan)) return KF_ERR_UNSUPPORTED;
+  return check_layout(job_of(*b));
+}
+
+static kf_status run_job(Op op, int stages, const Job& j, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if ((stages & ST_PREPARE) && (!j.F || !j.Q || !j.H || !j.R || !j.m0 || !j.P0))
     return KF_ERR_INVALID_ARG;
-  return KF_OK;
+  if ((stages & (ST_FORWARD | ST_BACKWARD)) && (!j.y || !j.m_filt || !j.P_filt))
+    return KF_ERR_INVALID_ARG;
+  if (op != OP_FILTER && (stages & ST_BACKWARD) && (!j.m_smooth || !j.P_smooth))
+    return KF_ERR_INVALID_ARG;
+  if (j.batch && (!j.len || !j.row)) return KF_ERR_INVALID_ARG;
+  const Layout L = make_layout(j);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
+    return KF_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  switch (j.precision) {
+    case KF_PREC_F64: return run_f64(op, stages, j, w, L, st);
+    case KF_PREC_F32: return run_f32(op, stages, j, w, L, st);
+    default: return run_mixed(op, stages, j, w, L, st);
+  }
 }
 
 static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws_bytes,
                      void* stream) {
   kf_status s = check_sizes(p);
   if (s != KF_OK) return s;
-  if ((stages & ST_PREPARE) && (!p->F || !p->Q || !p->H || !p->R || !p->m0 || !p->P0))
-    return KF_ERR_INVALID_ARG;
-  if ((stages & (ST_FORWARD | ST_BACKWARD)) && (!p->y || !p->m_filt || !p->P_filt))
-    return KF_ERR_INVALID_ARG;
-  if (op != OP_FILTER && (stages & ST_BACKWARD) && (!p->m_smooth || !p->P_smooth))
-    return KF_ERR_INVALID_ARG;
-  const Layout L = make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
-  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
-    return KF_ERR_WORKSPACE;
+  return run_job(op, stages, job_of(*p), ws, ws_bytes, stream);
+}
+
+static kf_status run_batch(Op op, const kf_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  kf_status s = check_batch(b);
+  if (s != KF_OK) return s;
+  return run_job(op, ST_ALL, job_of(*b), ws, ws_bytes, stream);
+}
+
+static kf_status read_error_words(const void* ws, size_t ws_bytes, unsigned (&words)[2],
+                                  void* stream) {
+  if (!ws || ws_bytes < 8 * sizeof(unsigned)) return KF_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
-  switch (p->precision) {
-    case KF_PREC_F64: return run_f64(op, stages, *p, w, L, st);
-    case KF_PREC_F32: return run_f32(op, stages, *p, w, L, st);
-    default: return run_mixed(op, stages, *p, w, L, st);
+  for (int slot = 0; slot < 2; ++slot) {
+    // the control words of scan slot s start at byte 16 s (kf_plan.hpp)
+    const char* src = static_cast<const char*>(ws) + 16 * slot + 2 * sizeof(unsigned);
+    if (hipMemcpyAsync(&words[slot], src, sizeof(unsigned), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+      return KF_ERR_DEVICE;
   }
+  if (hipStreamSynchronize(st) != hipSuccess) return KF_ERR_DEVICE;
+  return KF_OK;
 }
 
 }  // namespace kfs
@@ -97,7 +144,15 @@ kf_status kf_workspace_size(const kf_problem* p, size_t* bytes) {
   if (!bytes) return KF_ERR_INVALID_ARG;
   kf_status s = kfs::check_sizes(p);
   if (s != KF_OK) return s;
-  *bytes = kfs::make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq).total;
+  *bytes = kfs::make_layout(kfs::job_of(*p)).total;
+  return KF_OK;
+}
+
+kf_status kf_batch_workspace_size(const kf_batch* b, size_t* bytes) {
+  if (!bytes) return KF_ERR_INVALID_ARG;
+  kf_status s = kfs::check_batch(b);
+  if (s != KF_OK) return s;
+  *bytes = kfs::make_layout(kfs::job_of(*b)).total;
   return KF_OK;
 }
 
@@ -123,23 +178,38 @@ kf_status kf_device_copy(void* dst, const void* src, size_t bytes, void* stream)
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }
 
+kf_status kf_workspace_status(const void* ws, size_t ws_bytes, uint32_t* status, void* stream) {
+  if (!status) return KF_ERR_INVALID_ARG;
+  unsigned words[2] = {0u, 0u};
+  kf_status s = kfs::read_error_words(ws, ws_bytes, words, stream);
+  if (s != KF_OK) return s;
+  *status = words[0] | words[1];
+  return KF_OK;
+}
+
 kf_status kf_workspace_timed_out(const kf_problem* p, const void* ws, size_t ws_bytes,
                                  int32_t* timed_out, void* stream) {
   if (!timed_out) return KF_ERR_INVALID_ARG;
   kf_status s = kfs::check_sizes(p);
   if (s != KF_OK) return s;
-  const kfs::Layout L = kfs::make_layout(p->nx, p->ny, p->precision, p->scan, p->T, p->nseq);
-  if (!ws || ws_bytes < L.total) return KF_ERR_WORKSPACE;
+  if (ws_bytes < kfs::make_layout(kfs::job_of(*p)).total) return KF_ERR_WORKSPACE;
   unsigned words[2] = {0u, 0u};
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int slot = 0; slot < 2; ++slot) {
-    const char* src = static_cast<const char*>(ws) + L.ctr[slot] + 2 * sizeof(unsigned);
-    if (hipMemcpyAsync(&words[slot], src, sizeof(unsigned), hipMemcpyDeviceToHost, st) != hipSuccess)
-      return KF_ERR_DEVICE;
-  }
-  if (hipStreamSynchronize(st) != hipSuccess) return KF_ERR_DEVICE;
-  *timed_out = (words[0] | words[1]) ? 1 : 0;
+  s = kfs::read_error_words(ws, ws_bytes, words, stream);
+  if (s != KF_OK) return s;
+  *timed_out = ((words[0] | words[1]) & 1u) ? 1 : 0;
   return KF_OK;
+}
+
+kf_status kf_filter_batch(const kf_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run_batch(kfs::OP_FILTER, b, ws, ws_bytes, stream);
+}
+
+kf_status kf_smooth_rts_batch(const kf_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run_batch(kfs::OP_RTS, b, ws, ws_bytes, stream);
+}
+
+kf_status kf_smooth_twofilter_batch(const kf_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run_batch(kfs::OP_TWOFILTER, b, ws, ws_bytes, stream);
 }
 
 kf_status kf_filter(const kf_problem* p, void* ws, size_t ws_bytes, void* stream) {

@@ -25,26 +25,38 @@ template <int LMAX, class Fn> void with_items(int L, Fn&& fn) {
 }
 
 template <int N, int M, class P>
-kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
                     hipStream_t st) {
   using R = typename P::R;
   constexpr int B = kBlock;
   constexpr int IT = items_per_thread(N);
   constexpr int ITI = items_ti(N);
   R* cst = reinterpret_cast<R*>(ws + L.cst);
-  const size_t prep_blocks = (L.ctrl_words + 255) / 256;
+  size_t prep_blocks = (L.ctrl_words + 255) / 256;
+  if (prep_blocks > 1024) prep_blocks = 1024;
+  if ((long)prep_blocks < p.nmodels) prep_blocks = (size_t)p.nmodels;
   const bool generic = (p.scan == KF_SCAN_LOOKBACK_GENERIC);
+  const long cst_stride = (p.batch && p.nmodels > 1) ? L.cst_stride : 0;
   // the aggregate tables are built for the forward scan's L (unused by the
   // generic scan, whose L only sizes them)
-  if (stages & ST_PREPARE)
+  if (stages & ST_PREPARE) {
     with_items<ITI>(L.items[0], [&](auto c) {
-      hipLaunchKernelGGL((k_prepare<N, M, R, decltype(c)::value>),
-                         dim3(prep_blocks < 1024 ? prep_blocks : 1024), dim3(256), 0, st,
-                         static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+      hipLaunchKernelGGL((k_prepare<N, M, R, decltype(c)::value>), dim3((unsigned)prep_blocks),
+                         dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
                          static_cast<const R*>(p.H), static_cast<const R*>(p.R),
                          static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
-                         reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+                         reinterpret_cast<unsigned*>(ws), L.ctrl_words, p.nmodels, L.cst_stride);
     });
+    if (p.batch)
+      hipLaunchKernelGGL((k_batch_tiles<1024>), dim3(1), dim3(1024), 0, st, p.len, p.row, p.nseq,
+                         p.total_steps, (long)kBlock * L.items[0], (long)kBlock * L.items[1],
+                         reinterpret_cast<int64_t*>(ws + L.tile_start[0]),
+                         reinterpret_cast<int64_t*>(ws + L.tile_start[1]),
+                         reinterpret_cast<int*>(ws + L.tile_map[0]),
+                         reinterpret_cast<int*>(ws + L.tile_map[1]), L.grid[0], L.grid[1],
+                         reinterpret_cast<unsigned*>(ws + L.ctr[0]) + 2,
+                         reinterpret_cast<unsigned*>(ws + L.ctr[1]) + 2);
+  }
   const R* y = static_cast<const R*>(p.y);
   R* mf = static_cast<R*>(p.m_filt);
   R* Pf = static_cast<R*>(p.P_filt);
@@ -73,20 +85,27 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
     a.T = p.T;
     a.ntiles = L.ntiles[slot];
     a.nseq = p.nseq;
-    a.lb_group = lookback_group(a.ntiles);
+    a.lb_group = lookback_group(p.batch ? L.grid[slot] : a.ntiles);
+    if (p.batch) {
+      a.tile_seq = reinterpret_cast<const int*>(ws + L.tile_map[slot]);
+      a.tile_start = reinterpret_cast<const int64_t*>(ws + L.tile_start[slot]);
+      a.seq_len = p.len;
+      a.seq_row = p.row;
+      a.cst_stride = cst_stride;
+    }
     return a;
   };
-  auto grid = [&](const ScanArgs<R>& a) { return dim3((unsigned)(a.ntiles * a.nseq)); };
+  auto grid = [&](int slot) { return dim3((unsigned)L.grid[slot]); };
   if (stages & ST_FORWARD) {
     ScanArgs<R> fa = args(0);
     if (generic)
       with_items<IT>(L.items[0], [&](auto c) {
-        hipLaunchKernelGGL((k_filter<N, M, P, B, decltype(c)::value>), grid(fa), dim3(B), 0, st,
+        hipLaunchKernelGGL((k_filter<N, M, P, B, decltype(c)::value>), grid(0), dim3(B), 0, st,
                            fa, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
       });
     else
       with_items<ITI>(L.items[0], [&](auto c) {
-        hipLaunchKernelGGL((k_filter_ti<N, M, P, B, decltype(c)::value>), grid(fa), dim3(B), 0,
+        hipLaunchKernelGGL((k_filter_ti<N, M, P, B, decltype(c)::value>), grid(0), dim3(B), 0,
                            st, fa, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
       });
   }
@@ -95,10 +114,10 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
     with_items<IT>(L.items[1], [&](auto c) {
       constexpr int IL = decltype(c)::value;
       if (op == OP_RTS)
-        hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(ba), dim3(B), 0, st, ba, cst, y,
+        hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, cst, y,
                            (const R*)mf, (const R*)Pf, ms, Ps);
       else
-        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL>), grid(ba), dim3(B), 0, st, ba, cst, y,
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, cst, y,
                            (const R*)mf, (const R*)Pf, ms, Ps);
     });
   }
@@ -119,21 +138,21 @@ kf_status run_shape(Op op, int stages, const kf_problem& p, char* ws, const Layo
 // Each shape's launches are instantiated in a translation unit of their own
 // (kf_inst_<precision>_<group>.hip), so the library compiles in parallel.
 #define KFS_EXTERN(n, m)                                                                   \
-  extern template kf_status run_shape<n, m, PrecF64>(Op, int, const kf_problem&, char*,    \
+  extern template kf_status run_shape<n, m, PrecF64>(Op, int, const Job&, char*,    \
                                                      const Layout&, hipStream_t);          \
-  extern template kf_status run_shape<n, m, PrecF32>(Op, int, const kf_problem&, char*,    \
+  extern template kf_status run_shape<n, m, PrecF32>(Op, int, const Job&, char*,    \
                                                      const Layout&, hipStream_t);          \
-  extern template kf_status run_shape<n, m, PrecMixed>(Op, int, const kf_problem&, char*,  \
+  extern template kf_status run_shape<n, m, PrecMixed>(Op, int, const Job&, char*,  \
                                                        const Layout&, hipStream_t);
 KFS_SHAPES(KFS_EXTERN)
 #undef KFS_EXTERN
 
 #define KFS_INSTANTIATE(n, m, P)                                                           \
-  template kf_status run_shape<n, m, P>(Op, int, const kf_problem&, char*, const Layout&,  \
+  template kf_status run_shape<n, m, P>(Op, int, const Job&, char*, const Layout&,  \
                                         hipStream_t);
 
 template <class P>
-kf_status run_prec(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
+kf_status run_prec(Op op, int stages, const Job& p, char* ws, const Layout& L,
                    hipStream_t st) {
 #define KFS_CASE(n, m) \
   if (p.nx == n && p.ny == m) return run_shape<n, m, P>(op, stages, p, ws, L, st);

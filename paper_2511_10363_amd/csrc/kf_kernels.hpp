@@ -16,6 +16,8 @@
 // waits on belongs to a block that is already running.  The status words and
 // counters are zeroed by the preparation kernel that precedes the scans.
 #pragma once
+#include <cstdint>
+
 #include "kf_scan.hpp"
 
 namespace kfs {
@@ -43,7 +45,8 @@ template <int N, int M, int L = 1> struct CL {
 
 // The preparation launch also zeroes the workspace's control region (tile
 // tickets, epochs, timeout flags, look-back status words and payloads) with a
-// grid-stride loop.  In block 0, wavefront 0 derives the generic element and
+// grid-stride loop.  In block b < nmodels (one block per model of a batch,
+// block 0 alone for a shared model), wavefront 0 derives the generic element and
 // then the aggregate tables, each doubling step one Lemma 1 combine spread
 // over 16 lanes (mpart_combine_lanes), while wavefront 1 derives the first
 // element, so the FP64 chains overlap.
@@ -60,12 +63,22 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
                                                  const R* __restrict__ H_, const R* __restrict__ R_,
                                                  const R* __restrict__ m0_,
                                                  const R* __restrict__ P0_, R* __restrict__ cst,
-                                                 unsigned* __restrict__ ctrl, size_t ctrl_words) {
+                                                 unsigned* __restrict__ ctrl, size_t ctrl_words,
+                                                 long nmodels, long cst_stride) {
   static_assert((L & (L - 1)) == 0 && L <= 64, "aggregate length must be a power of two");
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ctrl_words;
        i += (size_t)gridDim.x * blockDim.x)
     ctrl[i] = 0u;
-  if (blockIdx.x != 0) return;
+  // block b derives model b (models are packed back to back)
+  const long mdl = blockIdx.x;
+  if (mdl >= nmodels) return;
+  F_ += mdl * N * N;
+  Q_ += mdl * N * N;
+  H_ += mdl * M * N;
+  R_ += mdl * M * M;
+  m0_ += mdl * N;
+  P0_ += mdl * N * N;
+  cst += mdl * cst_stride;
   using D = double;
   using LY = CL<N, M, L>;
   __shared__ MPart<N, D> sS[2];       // S_h, double-buffered
@@ -259,6 +272,89 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
 // own, which costs several times more.
 template <class R> KF_DEV void st_out(R* p, R v) { *p = v; }
 
+// Ragged batches: validate every sequence and lay out the tiles of both scan
+// slots, whose tiles hold tile0 and tile1 steps.  start[s][i] is the first
+// tile ticket of sequence i (start[s][nseq] the number of tiles), map[s][g]
+// the sequence of ticket g, -1 from the last tile up to the grid size bound[s].
+// A sequence with fewer than one step or rows outside [0, total_steps) gets no
+// tiles; if any sequence is invalid, or the valid lengths add up to more than
+// total_steps, bit 1 of both slots' error words is raised (and in the latter
+// case no sequence gets tiles), so no kernel ever touches rows outside the
+// arrays.  One block.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_tiles(
+    const int64_t* __restrict__ len, const int64_t* __restrict__ row, long nseq, long total_steps,
+    long tile0, long tile1, int64_t* __restrict__ start0, int64_t* __restrict__ start1,
+    int* __restrict__ map0, int* __restrict__ map1, long bound0, long bound1,
+    unsigned* __restrict__ err0, unsigned* __restrict__ err1) {
+  __shared__ long long s_a[BLOCK], s_b[BLOCK];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  auto valid = [&](long i) {
+    const long T = (long)len[i], r = (long)row[i];
+    return T >= 1 && T <= total_steps && r >= 0 && r <= total_steps - T;
+  };
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  long long part = 0;
+  int bad = 0;
+  for (long i = tid; i < nseq; i += BLOCK) {
+    if (valid(i)) part += (long long)len[i];
+    else bad = 1;
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  s_a[tid] = part;
+  __syncthreads();
+  for (int o = BLOCK / 2; o > 0; o >>= 1) {
+    if (tid < o) s_a[tid] += s_a[tid + o];
+    __syncthreads();
+  }
+  const bool over = s_a[0] > (long long)total_steps;
+  if (tid == 0 && (s_bad || over)) {
+    atomicOr(err0, 2u);
+    atomicOr(err1, 2u);
+  }
+  __syncthreads();
+  long long c0 = 0, c1 = 0;
+  for (long b = 0; b < nseq; b += BLOCK) {
+    const long i = b + tid;
+    long long n0 = 0, n1 = 0;
+    if (i < nseq && !over && valid(i)) {
+      n0 = ((long long)len[i] + tile0 - 1) / tile0;
+      n1 = ((long long)len[i] + tile1 - 1) / tile1;
+    }
+    s_a[tid] = n0;
+    s_b[tid] = n1;
+    __syncthreads();
+    for (int o = 1; o < BLOCK; o <<= 1) {
+      const long long x = (tid >= o) ? s_a[tid - o] : 0, y = (tid >= o) ? s_b[tid - o] : 0;
+      __syncthreads();
+      s_a[tid] += x;
+      s_b[tid] += y;
+      __syncthreads();
+    }
+    if (i < nseq) {
+      start0[i] = c0 + s_a[tid] - n0;
+      start1[i] = c1 + s_b[tid] - n1;
+    }
+    c0 += s_a[BLOCK - 1];
+    c1 += s_b[BLOCK - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    start0[nseq] = c0;
+    start1[nseq] = c1;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (long i = tid; i < nseq; i += BLOCK) {
+    for (long g = (long)start0[i]; g < (long)start0[i + 1]; ++g) map0[g] = (int)i;
+    for (long g = (long)start1[i]; g < (long)start1[i + 1]; ++g) map1[g] = (int)i;
+  }
+  for (long g = (long)c0 + tid; g < bound0; g += BLOCK) map0[g] = -1;
+  for (long g = (long)c1 + tid; g < bound1; g += BLOCK) map1[g] = -1;
+}
+
 // Look-back state and sizes shared by the scans (array pointers travel as
 // separate kernel parameters, see IO below).  agg and pre hold tagged words
 // (kf_scan.hpp): kWords<R> per scalar.
@@ -271,6 +367,27 @@ template <class R> struct ScanArgs {
   long ntiles;     // tiles per sequence
   long nseq;
   int lb_group;    // tiles per lane in a look-back window
+  // ragged batches (all null / zero for equal-length sequences):
+  const int* tile_seq;          // [grid] sequence of each tile ticket, -1 past the last tile
+  const int64_t* tile_start;    // [nseq + 1] first ticket of each sequence
+  const int64_t* seq_len;       // [nseq] steps of each sequence
+  const int64_t* seq_row;       // [nseq] first row of each sequence in y and the outputs
+  long cst_stride;              // scalars per model in cst when every sequence has its own
+};
+
+KF_DEV long uniform(long v) {
+  const unsigned long long u = (unsigned long long)v;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return (long)(((unsigned long long)hi << 32) | lo);
+}
+
+// The sequence a tile belongs to, as bound into a pipeline.
+struct SeqInfo {
+  long T;        // steps
+  long ntiles;   // tiles
+  long row0;     // first row in y and the outputs
+  long model;    // model index (0 when the model is shared)
 };
 
 // The kernels take the array pointers as separate __restrict__ parameters
@@ -400,18 +517,54 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   __shared__ R s_pre[PS];     // the tile's exclusive anchored state
   __shared__ E s_part[NW];    // look-back: wavefront partials of a window
   __shared__ int s_lp[NW];    // look-back: first lane of each wavefront with a published prefix
-  __shared__ long s_tile;
+  __shared__ long s_tile, s_seq, s_t, s_base;
+  __shared__ SeqInfo s_info;
   __shared__ unsigned s_tag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   if (tid == 0) {
-    s_tile = (long)atomicAdd(a.ctr, 1u);
+    const long g = (long)atomicAdd(a.ctr, 1u);
+    s_tile = g;
     s_tag = ld_relaxed(a.ctr + 3) + 1u;
+    SeqInfo si;
+    long sq, tt, bs;
+    if (a.tile_seq) {
+      sq = a.tile_seq[g];
+      if (sq >= 0) {
+        bs = (long)a.tile_start[sq];
+        tt = g - bs;
+        si.ntiles = (long)a.tile_start[sq + 1] - bs;
+        si.T = (long)a.seq_len[sq];
+        si.row0 = (long)a.seq_row[sq];
+        si.model = a.cst_stride ? sq : 0;
+      } else {
+        bs = tt = 0;
+        si = SeqInfo{0, 0, 0, 0};
+      }
+    } else {
+      sq = g / a.ntiles;
+      tt = g - sq * a.ntiles;
+      bs = sq * a.ntiles;
+      si = SeqInfo{a.T, a.ntiles, sq * a.T, 0};
+    }
+    s_seq = sq;
+    s_t = tt;
+    s_base = bs;
+    s_info = si;
   }
   __syncthreads();
   const long gt = s_tile;
   const unsigned tag = s_tag;
-  const long seq = gt / a.ntiles, t = gt - seq * a.ntiles;
-  pp.bind(seq, t, tid);
+  if (s_seq < 0) {  // a ragged batch's grid has spare blocks past the last tile
+    finish_grid(a.ctr, tag);
+    return;
+  }
+  // values read from LDS are the same in every lane; say so, so that the
+  // pointers built from them stay scalar
+  const long t = uniform(s_t);
+  const long base = uniform(s_base);
+  const SeqInfo si{uniform(s_info.T), uniform(s_info.ntiles), uniform(s_info.row0),
+                   uniform(s_info.model)};
+  pp.bind(si, t, tid);
   auto op = [&](const E& p, const E& q) { return pp.op(p, q); };
 
   // 1. thread fold
@@ -431,7 +584,6 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   //    published at once, before the look-back; so is tile 0's, and so is
   //    the prefix of a tile whose aggregate is itself an anchor.  Otherwise
   //    the tile aggregate is published first and the prefix after the look-back.
-  const long base = seq * a.ntiles;
   E tot;
   bool early = false;
   if (wid == 0) {
@@ -523,16 +675,18 @@ template <int N, int M, class P, int L> struct FilterPipe {
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
+  const R* __restrict__ cst;
   const R* __restrict__ y;
   R* __restrict__ mo;
   R* __restrict__ Po;
   KF_DEV FilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
-  KF_DEV void bind(long seq, long t, int tid) {
-    T = a.T;
+  KF_DEV void bind(const SeqInfo& s, long t, int tid) {
+    T = s.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
-    y = io.y + seq * T * M;
-    mo = io.m_out + seq * T * N;
-    Po = io.P_out + seq * T * N * N;
+    cst = io.cst + s.model * a.cst_stride;
+    y = io.y + s.row0 * M;
+    mo = io.m_out + s.row0 * N;
+    Po = io.P_out + s.row0 * N * N;
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
   KF_DEV void load_y(long k, R (&yk)[M]) const {
@@ -552,7 +706,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      E el = filter_element<N, M, R>(io.cst, k, yk);
+      E el = filter_element<N, M, R>(cst, k, yk);
       agg = (i == 0) ? el : fcombine<N, P>(agg, el);
     }
     return agg;
@@ -583,7 +737,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(io.cst, k, yk));
+      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(cst, k, yk));
       st_store_out(k, st);
     }
   }
@@ -629,16 +783,18 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
+  const R* __restrict__ cst;
   R* __restrict__ mo;
   R* __restrict__ Po;
   R yv[L][M];
   KF_DEV FilterTiPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
-  KF_DEV void bind(long seq, long t, int tid) {
-    T = a.T;
+  KF_DEV void bind(const SeqInfo& s, long t, int tid) {
+    T = s.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
-    const R* __restrict__ y = io.y + seq * T * M;
-    mo = io.m_out + seq * T * N;
-    Po = io.P_out + seq * T * N * N;
+    cst = io.cst + s.model * a.cst_stride;
+    const R* __restrict__ y = io.y + s.row0 * M;
+    mo = io.m_out + s.row0 * N;
+    Po = io.P_out + s.row0 * N * N;
 #pragma unroll
     for (int i = 0; i < L; ++i)
 #pragma unroll
@@ -646,7 +802,7 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
   KF_DEV E fold() const {
-    const R* __restrict__ c = io.cst;
+    const R* __restrict__ c = cst;
     E e;
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -673,9 +829,9 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
   KF_DEV void initial(St<N, R>& st) const {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      st.v[i] = io.cst[LY::m0 + i];
+      st.v[i] = cst[LY::m0 + i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) st.m[i][j] = io.cst[LY::P0 + i * N + j];
+      for (int j = 0; j < N; ++j) st.m[i][j] = cst[LY::P0 + i * N + j];
     }
   }
   KF_DEV void anchor(const E& e, St<N, R>& st) const {
@@ -698,15 +854,15 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        F[i][j] = io.cst[LY::F + i * N + j];
-        Q[i][j] = io.cst[LY::Q + i * N + j];
+        F[i][j] = cst[LY::F + i * N + j];
+        Q[i][j] = cst[LY::Q + i * N + j];
       }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) H[i][j] = io.cst[LY::H + i * N + j];
+      for (int j = 0; j < N; ++j) H[i][j] = cst[LY::H + i * N + j];
 #pragma unroll
-      for (int j = 0; j < M; ++j) Rm[i][j] = io.cst[LY::Rm + i * M + j];
+      for (int j = 0; j < M; ++j) Rm[i][j] = cst[LY::Rm + i * M + j];
     }
     // outputs leave in whole 128-byte lines where the sizes allow: the means
     // of MG consecutive steps, the covariances of PG consecutive steps
@@ -818,19 +974,21 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
+  const R* __restrict__ cst;
   const R* __restrict__ mf;
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
   KF_DEV RtsPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
-  KF_DEV void bind(long seq, long t, int tid) {
-    T = a.T;
-    const long tt = a.ntiles - 1 - t;
+  KF_DEV void bind(const SeqInfo& s, long t, int tid) {
+    T = s.T;
+    const long tt = s.ntiles - 1 - t;
     k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
-    mf = io.m_in + seq * T * N;
-    Pf = io.P_in + seq * T * N * N;
-    mo = io.m_out + seq * T * N;
-    Po = io.P_out + seq * T * N * N;
+    cst = io.cst + s.model * a.cst_stride;
+    mf = io.m_in + s.row0 * N;
+    Pf = io.P_in + s.row0 * N * N;
+    mo = io.m_out + s.row0 * N;
+    Po = io.P_out + s.row0 * N * N;
   }
   // p precedes q in scan order, so p is the later one in time
   KF_DEV E op(const E& p, const E& q) const { return scombine<N, P>(q, p); }
@@ -838,7 +996,7 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
     if (k >= 0 && k < T) load_state<N, R>(mf, Pf, k, x, Pk);
   }
   KF_DEV E element(long k, const R (&x)[N], const R (&Pk)[N][N]) const {
-    return rts_element<N, M, P>(io.cst, T, k, x, Pk);
+    return rts_element<N, M, P>(cst, T, k, x, Pk);
   }
   // Steps are walked last to first in groups of PG consecutive rows whose
   // covariances fill one 128-byte line (two rows at nx = 4 in FP32), with the
@@ -993,21 +1151,23 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
+  const R* __restrict__ cst;
   const R* __restrict__ y;
   const R* __restrict__ mf;
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
   KF_DEV TwoFilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
-  KF_DEV void bind(long seq, long t, int tid) {
-    T = a.T;
-    const long tt = a.ntiles - 1 - t;
+  KF_DEV void bind(const SeqInfo& s, long t, int tid) {
+    T = s.T;
+    const long tt = s.ntiles - 1 - t;
     k0 = tt * (long)(L * blockDim.x) + (long)(blockDim.x - 1 - tid) * L;
-    y = io.y + seq * T * M;
-    mf = io.m_in + seq * T * N;
-    Pf = io.P_in + seq * T * N * N;
-    mo = io.m_out + seq * T * N;
-    Po = io.P_out + seq * T * N * N;
+    cst = io.cst + s.model * a.cst_stride;
+    y = io.y + s.row0 * M;
+    mf = io.m_in + s.row0 * N;
+    Pf = io.P_in + s.row0 * N * N;
+    mo = io.m_out + s.row0 * N;
+    Po = io.P_out + s.row0 * N * N;
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(q, p); }
   // measurement of the element at row k: y_{k+2} (row k+1); none at k = T-1
@@ -1015,7 +1175,7 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
 #pragma unroll
     for (int c = 0; c < M; ++c) yk[c] = (k >= 0 && k + 1 < T) ? y[(k + 1) * M + c] : R(0);
   }
-  KF_DEV E element(long k, const R (&yk)[M]) const { return tf_element<N, M, R>(io.cst, T, k, yk); }
+  KF_DEV E element(long k, const R (&yk)[M]) const { return tf_element<N, M, R>(cst, T, k, yk); }
   KF_DEV E fold() const {
     E agg;
     set_identity(agg);

@@ -55,9 +55,64 @@ struct Layout {
   size_t tree[2];             // element buffers of the tree scans (Hillis-Steele: both)
   long tree_positions;        // scan positions per sequence of the tree scans
   int items[2];               // steps per thread of the forward and backward scans
-  long ntiles[2];             // tiles per sequence of the forward and backward scans
+  long ntiles[2];             // tiles per sequence (equal-length sequences)
+  long grid[2];               // blocks of the forward and backward scans
+  long cst_stride;            // scalars per model in the cst region
+  size_t tile_start[2];       // ragged batch: first tile ticket of each sequence, int64 [nseq+1]
+  size_t tile_map[2];         // ragged batch: sequence of each ticket, int32 [grid]
   size_t total;
 };
+
+// One call, equal-length sequences (kf_problem) or a ragged batch (kf_batch).
+struct Job {
+  int nx, ny, precision, scan;
+  long T;                     // steps per sequence (ragged batch: the mean, for tiling)
+  long nseq;
+  bool batch;
+  long nmodels;               // 1, or nseq in a batch with a model per sequence
+  long total_steps;           // rows of y and of the outputs
+  const int64_t* len;         // ragged batch, device [nseq]
+  const int64_t* row;         // ragged batch, device [nseq]
+  const void *F, *Q, *H, *R, *m0, *P0, *y;
+  void *m_filt, *P_filt, *m_smooth, *P_smooth;
+};
+
+inline Job job_of(const kf_problem& p) {
+  Job j{};
+  j.nx = p.nx;
+  j.ny = p.ny;
+  j.precision = p.precision;
+  j.scan = p.scan;
+  j.T = p.T;
+  j.nseq = p.nseq;
+  j.batch = false;
+  j.nmodels = 1;
+  j.total_steps = p.T * p.nseq;
+  j.F = p.F; j.Q = p.Q; j.H = p.H; j.R = p.R; j.m0 = p.m0; j.P0 = p.P0;
+  j.y = p.y;
+  j.m_filt = p.m_filt; j.P_filt = p.P_filt; j.m_smooth = p.m_smooth; j.P_smooth = p.P_smooth;
+  return j;
+}
+
+inline Job job_of(const kf_batch& b) {
+  Job j{};
+  j.nx = b.nx;
+  j.ny = b.ny;
+  j.precision = b.precision;
+  j.scan = b.scan;
+  j.nseq = b.nseq;
+  j.T = b.nseq > 0 ? (b.total_steps + b.nseq - 1) / b.nseq : 1;
+  if (j.T < 1) j.T = 1;
+  j.batch = true;
+  j.nmodels = b.nmodels;
+  j.total_steps = b.total_steps;
+  j.len = b.T;
+  j.row = b.offset;
+  j.F = b.F; j.Q = b.Q; j.H = b.H; j.R = b.R; j.m0 = b.m0; j.P0 = b.P0;
+  j.y = b.y;
+  j.m_filt = b.m_filt; j.P_filt = b.P_filt; j.m_smooth = b.m_smooth; j.P_smooth = b.P_smooth;
+  return j;
+}
 
 // Tiles per thread in a look-back window: one window of 256*G tiles reaches
 // back over a whole sequence of up to 1024 tiles.
@@ -77,20 +132,24 @@ inline long tree_positions_for(int scan, long T) {
   return p;
 }
 
-inline Layout make_layout(int nx, int ny, int precision, int scan, long T, long nseq) {
-  const size_t w = word_bytes(precision);
+inline Layout make_layout(const Job& j) {
+  const size_t w = word_bytes(j.precision);
   const size_t halves = w / 4;                           // tagged words per scalar
-  const long n = nx, m = ny;
+  const long n = j.nx, m = j.ny, T = j.T, nseq = j.nseq;
+  const int scan = j.scan;
   Layout L{};
   L.items[0] = (scan == KF_SCAN_LOOKBACK_GENERIC)
-                   ? choose_items(T, nseq, items_per_thread(nx), kTilesScan)
-                   : choose_items(T, nseq, items_ti(nx), kTilesTi);
-  L.items[1] = choose_items(T, nseq, items_per_thread(nx), kTilesScan);
-  L.ntiles[0] = ntiles_for(T, L.items[0]);
-  L.ntiles[1] = ntiles_for(T, L.items[1]);
-  const size_t ntf[2] = {(size_t)L.ntiles[0] * (size_t)nseq, (size_t)L.ntiles[1] * (size_t)nseq};
+                   ? choose_items(T, nseq, items_per_thread(j.nx), kTilesScan)
+                   : choose_items(T, nseq, items_ti(j.nx), kTilesTi);
+  L.items[1] = choose_items(T, nseq, items_per_thread(j.nx), kTilesScan);
+  for (int s = 0; s < 2; ++s) {
+    L.ntiles[s] = ntiles_for(T, L.items[s]);
+    // a ragged batch: sum over sequences of ceil(T_i / tile) <= nseq + total / tile
+    L.grid[s] = j.batch ? nseq + ntiles_for(j.total_steps, L.items[s]) : L.ntiles[s] * nseq;
+  }
   const size_t cst_words =                               // CL<N, M, L>::SIZE
-      10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(nx) * n * m;
+      10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(j.nx) * n * m;
+  L.cst_stride = (long)((cst_words + 63) & ~size_t(63));
   const size_t elem_words = 3 * n * n + 2 * n;           // largest element (filtering)
   const size_t pre_words = n + n * n;
   size_t off = 0;
@@ -100,19 +159,28 @@ inline Layout make_layout(int nx, int ny, int precision, int scan, long T, long 
   }
   for (int s = 0; s < 2; ++s) {
     L.flags[s] = off;
-    off += ntf[s] * sizeof(int);
+    off += (size_t)L.grid[s] * sizeof(int);
   }
   off = (off + 7) & ~size_t(7);
   for (int s = 0; s < 2; ++s) {
     L.agg[s] = off;
-    off += ntf[s] * elem_words * halves * 8;
+    off += (size_t)L.grid[s] * elem_words * halves * 8;
     L.pre[s] = off;
-    off += ntf[s] * pre_words * halves * 8;
+    off += (size_t)L.grid[s] * pre_words * halves * 8;
   }
   L.ctrl_words = off / 4;
   off = align256(off);
   L.cst = off;
-  off = align256(off + cst_words * w);
+  off = align256(off + (size_t)(j.batch ? j.nmodels : 1) * (size_t)L.cst_stride * w);
+  L.tile_start[0] = L.tile_start[1] = L.tile_map[0] = L.tile_map[1] = off;
+  if (j.batch) {
+    for (int s = 0; s < 2; ++s) {
+      L.tile_start[s] = off;
+      off = align256(off + (size_t)(nseq + 1) * sizeof(int64_t));
+      L.tile_map[s] = off;
+      off = align256(off + (size_t)L.grid[s] * sizeof(int));
+    }
+  }
   L.tree[0] = L.tree[1] = off;
   if (is_tree_scan(scan)) {
     L.tree_positions = tree_positions_for(scan, T);
@@ -132,12 +200,9 @@ enum Op { OP_FILTER = 0, OP_RTS = 1, OP_TWOFILTER = 2 };
 enum Stage { ST_PREPARE = 1, ST_FORWARD = 2, ST_BACKWARD = 4, ST_ALL = 7 };
 
 // Implemented once per precision (kf_inst_*.hip).
-kf_status run_f64(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
-                  hipStream_t st);
-kf_status run_f32(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
-                  hipStream_t st);
-kf_status run_mixed(Op op, int stages, const kf_problem& p, char* ws, const Layout& L,
-                    hipStream_t st);
+kf_status run_f64(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st);
+kf_status run_f32(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st);
+kf_status run_mixed(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st);
 bool shape_built(int nx, int ny);
 
 }  // namespace kfs

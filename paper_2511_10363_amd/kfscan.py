@@ -40,6 +40,17 @@ class KfProblem(ctypes.Structure):
                 ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
 
 
+class KfBatch(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("scan", ctypes.c_int32),
+                ("nseq", ctypes.c_int64), ("nmodels", ctypes.c_int64),
+                ("total_steps", ctypes.c_int64), ("T", _VOIDP), ("offset", _VOIDP),
+                ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
+                ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
+                ("m_filt", _VOIDP), ("P_filt", _VOIDP),
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+
+
 class KfScanError(RuntimeError):
     pass
 
@@ -49,7 +60,8 @@ _lock = threading.Lock()
 EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_size",
            "kf_workspace_clear", "kf_workspace_timed_out", "kf_device_copy", "kf_filter", "kf_smooth_rts",
            "kf_smooth_twofilter", "kf_prepare", "kf_pass_filter", "kf_pass_rts",
-           "kf_pass_twofilter")
+           "kf_pass_twofilter", "kf_batch_workspace_size", "kf_filter_batch",
+           "kf_smooth_rts_batch", "kf_smooth_twofilter_batch", "kf_workspace_status")
 STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
 # When set (the tests set it), every call synchronises and checks the
 # workspace's look-back timeout flag.
@@ -75,6 +87,15 @@ def load_library(path: str = LIB_PATH):
         lib.kf_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         lib.kf_workspace_clear.restype = ctypes.c_int
         lib.kf_workspace_clear.argtypes = [_VOIDP, ctypes.c_size_t, _VOIDP]
+        B = ctypes.POINTER(KfBatch)
+        lib.kf_batch_workspace_size.restype = ctypes.c_int
+        lib.kf_batch_workspace_size.argtypes = [B, ctypes.POINTER(ctypes.c_size_t)]
+        for name in ("kf_filter_batch", "kf_smooth_rts_batch", "kf_smooth_twofilter_batch"):
+            getattr(lib, name).restype = ctypes.c_int
+            getattr(lib, name).argtypes = [B, _VOIDP, ctypes.c_size_t, _VOIDP]
+        lib.kf_workspace_status.restype = ctypes.c_int
+        lib.kf_workspace_status.argtypes = [_VOIDP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32),
+                                            _VOIDP]
         lib.kf_device_copy.restype = ctypes.c_int
         lib.kf_device_copy.argtypes = [_VOIDP, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_workspace_timed_out.restype = ctypes.c_int
@@ -224,6 +245,104 @@ def smooth_rts(model, y, precision="f32", scan="auto", workspace=None):
 def smooth_twofilter(model, y, precision="f32", scan="auto", workspace=None):
     """Algorithm 7.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
     return _smoother("kf_smooth_twofilter", model, y, precision, scan, workspace)
+
+
+def make_batch(models, y, T, offset, precision="f32", scan="auto", smoother=False):
+    """Fill a KfBatch for a ragged batch.  ``models`` holds F, Q, H, R, m0, P0 of
+    one shared model, or each with a leading [nseq] dimension (one model per
+    sequence); ``y`` is the packed [total_steps, ny] measurements; ``T`` and
+    ``offset`` are int64 GPU tensors [nseq] (length and first row of each
+    sequence).  Returns (batch, keepalive) with the outputs in keepalive."""
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % list(PRECISIONS))
+    if scan not in SCANS:
+        raise ValueError("scan must be one of %s" % list(SCANS))
+    dt = dtype_for(precision)
+    F, Q, H, R, m0, P0 = _model_tensors(models)
+    if y.dim() != 2:
+        raise ValueError("y must be packed as [total_steps, ny]")
+    dev = y.device
+    if dev.type != "cuda":
+        raise KfScanError("kfscan runs on the GPU only; y is on %s" % dev)
+    total, ny = y.shape
+    nx = F.shape[-1]
+    nseq = T.shape[0]
+    nmodels = F.shape[0] if F.dim() == 3 else 1
+    lead = (nmodels,) if F.dim() == 3 else ()
+    shapes = {"F": (F, (nx, nx)), "Q": (Q, (nx, nx)), "H": (H, (ny, nx)), "R": (R, (ny, ny)),
+              "m0": (m0, (nx,)), "P0": (P0, (nx, nx))}
+    for name, (t, shp) in shapes.items():
+        if tuple(t.shape) != lead + shp:
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), lead + shp))
+        if t.device != dev or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dt, dev))
+    for name, t in (("T", T), ("offset", offset)):
+        if t.shape != (nseq,) or t.dtype != torch.int64 or t.device != dev or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous int64 [nseq] tensor on %s" % (name, dev))
+    if y.dtype != dt or not y.is_contiguous():
+        raise ValueError("y must be a contiguous %s tensor" % dt)
+    keep = dict(y=y, T=T, offset=offset,
+                m_filt=torch.empty((total, nx), dtype=dt, device=dev),
+                P_filt=torch.empty((total, nx, nx), dtype=dt, device=dev),
+                m_smooth=None, P_smooth=None)
+    if smoother:
+        keep["m_smooth"] = torch.empty((total, nx), dtype=dt, device=dev)
+        keep["P_smooth"] = torch.empty((total, nx, nx), dtype=dt, device=dev)
+    b = KfBatch()
+    b.nx, b.ny, b.precision, b.scan = nx, ny, PRECISIONS[precision], SCANS[scan]
+    b.nseq, b.nmodels, b.total_steps = nseq, nmodels, total
+    b.T, b.offset = T.data_ptr(), offset.data_ptr()
+    b.F, b.Q, b.H, b.R = F.data_ptr(), Q.data_ptr(), H.data_ptr(), R.data_ptr()
+    b.m0, b.P0, b.y = m0.data_ptr(), P0.data_ptr(), y.data_ptr()
+    b.m_filt, b.P_filt = keep["m_filt"].data_ptr(), keep["P_filt"].data_ptr()
+    if smoother:
+        b.m_smooth, b.P_smooth = keep["m_smooth"].data_ptr(), keep["P_smooth"].data_ptr()
+    return b, keep
+
+
+def batch_workspace_size(b: KfBatch) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().kf_batch_workspace_size(ctypes.byref(b), ctypes.byref(n)),
+           "kf_batch_workspace_size")
+    return n.value
+
+
+def workspace_status(ws: torch.Tensor) -> int:
+    """Error bits of the last call on this workspace (synchronises the current
+    stream): 1 = a look-back wait gave up, 2 = invalid ragged-batch entries."""
+    flag = ctypes.c_uint32(0)
+    stream = torch.cuda.current_stream(ws.device).cuda_stream
+    _check(load_library().kf_workspace_status(ws.data_ptr(), ws.numel() * ws.element_size(),
+                                              ctypes.byref(flag), stream), "kf_workspace_status")
+    return flag.value
+
+
+def run_batch(entry, b: KfBatch, device, workspace=None):
+    """Enqueue kf_filter_batch / kf_smooth_rts_batch / kf_smooth_twofilter_batch."""
+    lib = load_library()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    need = batch_workspace_size(b)
+    ws = workspace if workspace is not None else Workspace.get(device, stream, need)
+    nbytes = ws.numel() * ws.element_size()
+    if nbytes < need:
+        raise KfScanError("workspace of %d bytes is smaller than the %d needed" % (nbytes, need))
+    _check(getattr(lib, entry)(ctypes.byref(b), ws.data_ptr(), nbytes, stream), entry)
+    if CHECK and workspace_status(ws) & 1:
+        raise KfScanError("%s: a look-back wait timed out; outputs are invalid" % entry)
+    return ws
+
+
+def batch(entry, models, y, T, offset, precision="f32", scan="auto", workspace=None):
+    """One ragged-batch call; entry is "filter", "rts" or "tf".  Returns the
+    packed outputs (m_filt, P_filt[, m_smooth, P_smooth]) and the workspace."""
+    name = {"filter": "kf_filter_batch", "rts": "kf_smooth_rts_batch",
+            "tf": "kf_smooth_twofilter_batch"}[entry]
+    b, keep = make_batch(models, y, T, offset, precision, scan, smoother=(entry != "filter"))
+    ws = run_batch(name, b, y.device, workspace)
+    outs = (keep["m_filt"], keep["P_filt"])
+    if entry != "filter":
+        outs += (keep["m_smooth"], keep["P_smooth"])
+    return outs, ws
 
 
 class Plan:

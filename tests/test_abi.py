@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(kfscan):
 
 def test_abi_version_and_status_strings(kfscan):
     lib = kfscan.load_library()
-    assert lib.kf_abi_version() == 1
+    assert lib.kf_abi_version() == 2
     for code in range(5):
         assert kfscan.status_string(code)
 
@@ -85,3 +85,42 @@ def test_entry_points_reject_before_launch(kfscan):
 def test_supported_shapes(kfscan):
     assert kfscan.supported(4, 2, "f32") and kfscan.supported(4, 2, "f64")
     assert not kfscan.supported(5, 2, "f32")
+
+
+def _batch(kfscan, nx=4, ny=2, prec=1, nseq=100, nmodels=1, total=300000, scan=0):
+    b = kfscan.KfBatch()
+    b.nx, b.ny, b.precision, b.scan = nx, ny, prec, scan
+    b.nseq, b.nmodels, b.total_steps = nseq, nmodels, total
+    return b
+
+
+def test_batch_workspace_size_and_validation(kfscan):
+    """Ragged batches: host-side checks of kf_batch_workspace_size."""
+    lib = kfscan.load_library()
+    n = ctypes.c_size_t(0)
+    size = lambda b: lib.kf_batch_workspace_size(ctypes.byref(b), ctypes.byref(n))  # noqa: E731
+    assert size(_batch(kfscan)) == 0 and n.value > 0 and n.value % 256 == 0
+    shared = n.value
+    assert size(_batch(kfscan, nmodels=100)) == 0 and n.value > shared   # a model per sequence
+    assert size(_batch(kfscan, nmodels=7)) == 1          # neither shared nor one per sequence
+    assert size(_batch(kfscan, nseq=0)) == 1
+    assert size(_batch(kfscan, nseq=(1 << 22) + 1)) == 1
+    assert size(_batch(kfscan, total=0)) == 1
+    assert size(_batch(kfscan, nx=5)) == 2
+    assert size(_batch(kfscan, scan=2)) == 2            # tree scans are not offered for batches
+    assert size(_batch(kfscan, prec=9)) == 1
+    assert lib.kf_batch_workspace_size(None, ctypes.byref(n)) == 1
+
+
+def test_batch_entry_points_reject_before_launch(kfscan):
+    lib = kfscan.load_library()
+    b = _batch(kfscan)
+    for name in ("kf_filter_batch", "kf_smooth_rts_batch", "kf_smooth_twofilter_batch"):
+        assert getattr(lib, name)(ctypes.byref(b), None, 0, None) == 1   # null pointers
+    for f in ("F", "Q", "H", "R", "m0", "P0", "y", "m_filt", "P_filt", "m_smooth", "P_smooth"):
+        setattr(b, f, 4096)
+    assert lib.kf_filter_batch(ctypes.byref(b), None, 0, None) == 1      # T, offset still null
+    b.T, b.offset = 4096, 8192
+    assert lib.kf_filter_batch(ctypes.byref(b), None, 0, None) == 3      # no workspace
+    status = ctypes.c_uint32(0)
+    assert lib.kf_workspace_status(None, 0, ctypes.byref(status), None) == 3
