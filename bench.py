@@ -83,6 +83,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
+    ap.add_argument("--workload", default="tracking", choices=["tracking", "batched"],
+                    help="tracking: one long sequence (the headline); batched: 4096 ragged "
+                         "sequences, a random stable model each")
+    ap.add_argument("--nseq", type=int, default=4096, help="sequences of the batched workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -99,6 +103,8 @@ def main() -> int:
     kfscan.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "batched":
+        return bench_batched(args, np, torch, W, kfscan, dev)
     T = args.T if args.T > 0 else 1 << args.log2T
     tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
@@ -235,6 +241,131 @@ def main() -> int:
                       kback: float(t_back.mean())},
         "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
         "copy_GBps": copy_gbps,
+        "errors_vs_oracle": errors,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_batched(args, np, torch, W, kfscan, dev) -> int:
+    """4096 sequences, T_i = round(2^U) with U ~ U[6, 14], a random stable model
+    each (rho = 0.95, Q = 0.1 I, H Gaussian, R = 0.5 I, m0 = 0, P0 = I), nx
+    uniform on {2, 4} with ny = nx / 2, filter + RTS smoother.  One
+    kf_smooth_rts_batch call per (nx, ny) group per step; value = sum of T_i per
+    second.  (nx = 8 is not built: its register-resident elements exceed the
+    VGPR budget of these kernels.)"""
+    import concurrent.futures as cf
+
+    prec = args.precision
+    dt = kfscan.dtype_for(prec)
+    w = 8 if prec == "f64" else 4
+    seqs = W.ragged_batch(nseq=args.nseq, nx_choices=(2, 4), seed=args.seed)
+    groups = {}
+    for i, (model, y) in enumerate(seqs):
+        groups.setdefault((model.nx, model.ny), []).append(i)
+    calls = []
+    total_steps = 0
+    alg_bytes = 0
+    for (nx, ny), idx in sorted(groups.items()):
+        lengths = np.array([len(seqs[i][1]) for i in idx], dtype=np.int64)
+        offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+        y = np.concatenate([seqs[i][1] for i in idx])
+        parts = [np.stack([seqs[i][0].arrays()[j] for i in idx]) for j in range(6)]
+        dm = tuple(torch.as_tensor(p).to(dev, dt).contiguous() for p in parts)
+        yd = torch.as_tensor(y).to(dev, dt).contiguous()
+        Td = torch.as_tensor(lengths).to(dev)
+        od = torch.as_tensor(offsets).to(dev)
+        b, keep = kfscan.make_batch(dm, yd, Td, od, prec, smoother=True)
+        ws = torch.empty(max(kfscan.batch_workspace_size(b), 1 << 20), dtype=torch.uint8,
+                         device=dev)
+        calls.append((b, keep, ws, dm, yd, Td, od, idx, offsets, lengths))
+        total_steps += int(lengths.sum())
+        alg_bytes += int(lengths.sum()) * w * (ny + 2 * nx + 2 * nx * nx)
+
+    def one_pass():
+        for c in calls:
+            kfscan.run_batch("kf_smooth_rts_batch", c[0], dev, c[2])
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    for c in calls:
+        if kfscan.workspace_status(c[2]):
+            raise RuntimeError("batched workload: a batch entry was refused")
+    K = args.steps
+    every = max(1, args.event_every)
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        if i % every == 0:
+            e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            e[0].record()
+            one_pass()
+            e[1].record()
+            evs.append(e)
+        else:
+            one_pass()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = total_steps * K / wall
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    achieved = alg_bytes / (lat.mean() * 1e-3) / 1e9
+
+    cpu = None
+    errors = None
+    if args.cpu_seconds > 0:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        rng = np.random.default_rng(1)
+        cast = (lambda a: a) if prec == "f64" else (
+            lambda a: np.asarray(a, dtype=np.float32).astype(np.float64))
+
+        def run_one(i):
+            model, y = seqs[i]
+            return oracle.smooth_rts(*(cast(a) for a in model.arrays()), cast(y))
+        # whole passes over random subsets until the time budget is spent
+        done_steps = 0
+        c0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+            while time.perf_counter() - c0 < args.cpu_seconds:
+                pick = rng.choice(len(seqs), size=min(len(seqs), 8 * cores), replace=False)
+                list(ex.map(run_one, pick))
+                done_steps += sum(len(seqs[i][1]) for i in pick)
+        c1 = time.perf_counter()
+        cpu = {"value": done_steps / (c1 - c0), "unit": "steps/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "sequential FP64 filter + RTS smoother over random sequences of the "
+                         "batch, one sequence per host thread, %d steps" % done_steps}
+        # accuracy on a few sequences of each group
+        worst = {"m_filt": 0.0, "P_filt": 0.0, "m_smooth": 0.0, "P_smooth": 0.0}
+        for c in calls:
+            keep, idx, offsets, lengths = c[1], c[7], c[8], c[9]
+            outs = [keep[k].double().cpu().numpy() for k in ("m_filt", "P_filt", "m_smooth",
+                                                             "P_smooth")]
+            for j in range(0, len(idx), max(1, len(idx) // 16)):
+                ref = run_one(idx[j])
+                a, b = offsets[j], offsets[j] + lengths[j]
+                for name, g, r in zip(worst, outs, ref):
+                    e = float(np.max(np.abs(g[a:b] - r)) / max(np.max(np.abs(r)), 1e-300))
+                    worst[name] = max(worst[name], e)
+        errors = worst
+
+    out = {
+        "metric": "batched filter+smoother steps/s (4096 ragged sequences)",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "ragged_batch_%d_T2^U6-14_nx2,4" % args.nseq,
+                   "sequences": args.nseq, "total_steps": total_steps,
+                   "groups": {"%dx%d" % k: len(v) for k, v in sorted(groups.items())},
+                   "pipeline": "kf_smooth_rts_batch per shape group", "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole pass"},
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))
