@@ -85,7 +85,6 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
     a.T = p.T;
     a.ntiles = L.ntiles[slot];
     a.nseq = p.nseq;
-    a.lb_group = lookback_group(p.batch ? L.grid[slot] : a.ntiles);
     if (p.batch) {
       a.tile_seq = reinterpret_cast<const int*>(ws + L.tile_map[slot]);
       a.tile_start = reinterpret_cast<const int64_t*>(ws + L.tile_start[slot]);

@@ -366,7 +366,6 @@ template <class R> struct ScanArgs {
   long T;
   long ntiles;     // tiles per sequence
   long nseq;
-  int lb_group;    // tiles per lane in a look-back window
   // ragged batches (all null / zero for equal-length sequences):
   const int* tile_seq;          // [grid] sequence of each tile ticket, -1 past the last tile
   const int64_t* tile_start;    // [nseq + 1] first ticket of each sequence
@@ -628,8 +627,12 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
       tag_load<R>(sp, a.pre + (base + idx) * PSW, tag, a.ctr + 2);
       pp.expand(sp, v);
     };
-    ex = lookback<BLOCK, E>(a.flags + base, a.ctr + 2, tag, t, a.lb_group, op, load_agg, expand,
-                            s_part, s_lp);
+    // tiles per thread in a look-back window: one window of BLOCK*G tiles
+    // reaches back over a whole sequence of up to 4*BLOCK tiles
+    const long g = (si.ntiles + BLOCK - 1) / BLOCK;
+    const int G = (int)(g < 1 ? 1 : (g > 4 ? 4 : g));
+    ex = lookback<BLOCK, E>(a.flags + base, a.ctr + 2, tag, t, G, op, load_agg, expand, s_part,
+                            s_lp);
   }
   if (wid == 0 && t > 0) {
     St<N, R> st;

@@ -114,13 +114,6 @@ inline Job job_of(const kf_batch& b) {
   return j;
 }
 
-// Tiles per thread in a look-back window: one window of 256*G tiles reaches
-// back over a whole sequence of up to 1024 tiles.
-inline int lookback_group(long ntiles) {
-  const long g = (ntiles + kBlock - 1) / kBlock;
-  return (int)(g < 1 ? 1 : (g > 4 ? 4 : g));
-}
-
 inline bool is_tree_scan(int scan) {
   return scan == KF_SCAN_BLELLOCH || scan == KF_SCAN_HILLIS_STEELE;
 }
@@ -138,10 +131,14 @@ inline Layout make_layout(const Job& j) {
   const long n = j.nx, m = j.ny, T = j.T, nseq = j.nseq;
   const int scan = j.scan;
   Layout L{};
-  L.items[0] = (scan == KF_SCAN_LOOKBACK_GENERIC)
-                   ? choose_items(T, nseq, items_per_thread(j.nx), kTilesScan)
-                   : choose_items(T, nseq, items_ti(j.nx), kTilesTi);
-  L.items[1] = choose_items(T, nseq, items_per_thread(j.nx), kTilesScan);
+  // A ragged batch always takes the longest tiles, so that each sequence is
+  // tiled, scanned and rounded the same whatever else is in the batch.
+  const int lf = (scan == KF_SCAN_LOOKBACK_GENERIC) ? items_per_thread(j.nx) : items_ti(j.nx);
+  const int lb = items_per_thread(j.nx);
+  L.items[0] = j.batch ? lf
+                       : choose_items(T, nseq, lf,
+                                      scan == KF_SCAN_LOOKBACK_GENERIC ? kTilesScan : kTilesTi);
+  L.items[1] = j.batch ? lb : choose_items(T, nseq, lb, kTilesScan);
   for (int s = 0; s < 2; ++s) {
     L.ntiles[s] = ntiles_for(T, L.items[s]);
     // a ragged batch: sum over sequences of ceil(T_i / tile) <= nseq + total / tile

@@ -145,10 +145,32 @@ def test_invalid_entries_are_skipped_and_reported():
     assert k.workspace_status(ws) == 0
 
 
-def test_one_sequence_batch_equals_plain_call():
-    """A batch of one sequence gives bit-identical results to kf_smooth_rts."""
+@pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
+def test_results_do_not_depend_on_the_rest_of_the_batch(entry):
+    """A sequence's outputs are bit-identical whether it is processed alone or
+    packed with others (different lengths, models and positions): batches
+    always take the longest tiles, and each sequence's look-back depends only
+    on its own tiles."""
     k = kfscan()
-    model, y = W.tracking(50000, seed=9)
+    lengths = [5000, 300, 70000, 1, 2500, 9000]
+    models, ys, offsets, total = _case(lengths, 4, 2, True, seed=21)
+    dm, yd, T, off = _device_batch(models, ys, offsets, total, True, "f32")
+    mixed, _ = k.batch(entry, dm, yd, T, off, precision="f32")
+    for i in (0, 2, 3):
+        one_m = tuple(t[i:i + 1].contiguous() for t in dm)
+        y1 = yd[offsets[i]:offsets[i] + lengths[i]].contiguous()
+        alone, _ = k.batch(entry, one_m, y1, T[i:i + 1].contiguous(),
+                           torch.zeros(1, dtype=torch.int64, device="cuda"), precision="f32")
+        torch.cuda.synchronize()
+        for a, b in zip(alone, mixed):
+            assert torch.equal(a, b[offsets[i]:offsets[i] + lengths[i]]), (entry, i)
+
+
+def test_one_sequence_batch_equals_plain_call():
+    """A batch of one sequence gives bit-identical results to kf_smooth_rts at a
+    length where both take the longest tiles."""
+    k = kfscan()
+    model, y = W.tracking(1 << 20, seed=9)
     dm = k.model_to_device(model.arrays(), "f32")
     yd = torch.as_tensor(y).to("cuda", torch.float32).contiguous()
     plain = k.smooth_rts(dm, yd, precision="f32")
