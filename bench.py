@@ -83,9 +83,11 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
-    ap.add_argument("--workload", default="tracking", choices=["tracking", "batched"],
+    ap.add_argument("--workload", default="tracking", choices=["tracking", "batched", "serving"],
                     help="tracking: one long sequence (the headline); batched: 4096 ragged "
-                         "sequences, a random stable model each")
+                         "sequences, a random stable model each; serving: Poisson job "
+                         "arrivals served in ragged batches")
+    ap.add_argument("--jobs", type=int, default=2000, help="jobs of the serving workload")
     ap.add_argument("--nseq", type=int, default=4096, help="sequences of the batched workload")
     args = ap.parse_args()
 
@@ -105,6 +107,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.workload == "batched":
         return bench_batched(args, np, torch, W, kfscan, dev)
+    if args.workload == "serving":
+        return bench_serving(args, np, torch, W, kfscan, dev)
     T = args.T if args.T > 0 else 1 << args.log2T
     tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
@@ -366,6 +370,133 @@ def bench_batched(args, np, torch, W, kfscan, dev) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole pass"},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "errors_vs_oracle": errors,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_serving(args, np, torch, W, kfscan, dev) -> int:
+    """Serving: jobs arrive as a Poisson process; whenever the GPU is free, every
+    job that has arrived is dispatched as one ragged batch (filter + RTS, a model
+    per job, kf_smooth_rts_batch).  Jobs: T = round(2^U), U ~ U[10, 16], nx = 4,
+    ny = 2, random stable F (rho = 0.98), Q = 0.05 I, H Gaussian, R = 0.2 I, FP32.
+    Inputs and outputs stay resident on the GPU; a dispatch uploads only the
+    jobs' lengths, rows and model indices.  First the saturated rate is measured
+    (all jobs in batches of up to 256), then arrivals at 0.5, 0.8 and 0.95 of it;
+    latency = time the host sees the job's batch finished - arrival time.  The
+    survey's serving workload has nx = 16, which is not built; this runs the
+    same protocol at nx = 4."""
+    prec = args.precision
+    dt = kfscan.dtype_for(prec)
+    rng = np.random.default_rng(args.seed)
+    n = args.jobs
+    lengths = np.array(W.log_uniform_lengths(n, 10.0, 16.0, rng), dtype=np.int64)
+    rows = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+    total = int(lengths.sum())
+    models = [W.random_stable_model(4, 2, 0.98, 0.05, 0.2, rng) for _ in range(n)]
+    y = np.empty((total, 2))
+    for i in range(n):
+        y[rows[i]:rows[i] + lengths[i]] = W.simulate(models[i], int(lengths[i]), rng)
+    dm_all = [torch.as_tensor(np.stack([m.arrays()[j] for m in models])).to(dev, dt).contiguous()
+              for j in range(6)]
+    yd = torch.as_tensor(y).to(dev, dt).contiguous()
+    del y
+    Td_all = torch.as_tensor(lengths).to(dev)
+    rows_all = torch.as_tensor(rows).to(dev)
+    outs = {k: torch.empty(shape, dtype=dt, device=dev) for k, shape in
+            (("m_filt", (total, 4)), ("P_filt", (total, 4, 4)), ("m_smooth", (total, 4)),
+             ("P_smooth", (total, 4, 4)))}
+    max_batch = 256
+    # one workspace sized for the largest possible batch
+    probe = kfscan.KfBatch()
+    probe.nx, probe.ny, probe.precision, probe.scan = 4, 2, kfscan.PRECISIONS[prec], 0
+    probe.nseq, probe.nmodels, probe.total_steps = max_batch, max_batch, total
+    ws = torch.empty(kfscan.batch_workspace_size(probe), dtype=torch.uint8, device=dev)
+
+    def dispatch(idx):
+        idx_d = torch.as_tensor(np.asarray(idx, dtype=np.int64)).to(dev, non_blocking=False)
+        mods = [t.index_select(0, idx_d).contiguous() for t in dm_all]
+        b = kfscan.KfBatch()
+        b.nx, b.ny, b.precision, b.scan = 4, 2, kfscan.PRECISIONS[prec], 0
+        b.nseq, b.nmodels, b.total_steps = len(idx), len(idx), total
+        Tb = Td_all.index_select(0, idx_d).contiguous()
+        ob = rows_all.index_select(0, idx_d).contiguous()
+        b.T, b.offset = Tb.data_ptr(), ob.data_ptr()
+        b.F, b.Q, b.H, b.R, b.m0, b.P0 = (t.data_ptr() for t in mods)
+        b.y = yd.data_ptr()
+        b.m_filt, b.P_filt = outs["m_filt"].data_ptr(), outs["P_filt"].data_ptr()
+        b.m_smooth, b.P_smooth = outs["m_smooth"].data_ptr(), outs["P_smooth"].data_ptr()
+        kfscan.run_batch("kf_smooth_rts_batch", b, dev, ws)
+        ev = torch.cuda.Event()
+        ev.record()
+        return ev, (mods, Tb, ob)
+
+    # saturated rate: all jobs, back to back, batches of max_batch
+    for _ in range(2):
+        dispatch(list(range(min(n, max_batch))))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keep = []
+    for s0 in range(0, n, max_batch):
+        keep.append(dispatch(list(range(s0, min(n, s0 + max_batch)))))
+    torch.cuda.synchronize()
+    sat_s = time.perf_counter() - t0
+    sat_jobs = n / sat_s
+    if kfscan.workspace_status(ws):
+        raise RuntimeError("serving: a batch entry was refused")
+    results = []
+    for frac in (0.5, 0.5, 0.8, 0.95):   # the first run warms the allocator and is dropped
+        arrivals = W.poisson_arrivals(n, frac * sat_jobs, np.random.default_rng(args.seed + 1))
+        done_at = np.zeros(n)
+        nxt = 0
+        inflight = None
+        batches = 0
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            if inflight is not None and inflight[0].query():
+                done_at[inflight[2]] = time.perf_counter() - t0
+                inflight = None
+            if inflight is None:
+                hi = int(np.searchsorted(arrivals, now, side="right"))
+                if hi > nxt:
+                    idx = list(range(nxt, min(hi, nxt + max_batch)))
+                    ev, hold = dispatch(idx)
+                    inflight = (ev, hold, idx)
+                    nxt = idx[-1] + 1
+                    batches += 1
+                elif nxt >= n:
+                    break
+        lat = (done_at - arrivals) * 1e3
+        results.append({"load": frac, "rate_jobs_per_s": frac * sat_jobs,
+                        "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_batch": n / batches,
+                        "steps_per_s": total / (done_at.max() - arrivals[0])})
+    results = results[1:]
+    errors = None
+    if args.cpu_seconds > 0:
+        import oracle
+        worst = 0.0
+        mf = outs["m_smooth"]
+        for i in range(0, n, max(1, n // 8)):
+            cast = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+            yi = yd[rows[i]:rows[i] + lengths[i]].double().cpu().numpy()
+            ref = oracle.smooth_rts(*(cast(a) for a in models[i].arrays()), yi)
+            g = mf[rows[i]:rows[i] + lengths[i]].double().cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(g - ref[2])) / np.max(np.abs(ref[2]))))
+        errors = {"m_smooth": worst}
+    out = {
+        "metric": "serving: saturated steps/s and p50/p99 job latency under Poisson arrivals",
+        "value": total * n / (n * sat_s), "unit": "steps/s", "n_gpus": 1, "steps": n,
+        "warmup": 2, "ms_per_step": sat_s / n * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "serving_%d_jobs_T2^U10-16_nx4_ny2" % n, "jobs": n,
+                   "total_steps": total, "max_batch": max_batch, "seed": args.seed},
+        "saturated_jobs_per_s": sat_jobs,
+        "poisson": results,
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))
