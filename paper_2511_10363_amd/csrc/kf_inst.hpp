@@ -40,12 +40,16 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
   // the aggregate tables are built for the forward scan's L (unused by the
   // generic scan, whose L only sizes them)
   if (stages & ST_PREPARE) {
-    with_items<ITI>(L.items[0], [&](auto c) {
-      hipLaunchKernelGGL((k_prepare<N, M, R, decltype(c)::value>), dim3((unsigned)prep_blocks),
-                         dim3(256), 0, st, static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
-                         static_cast<const R*>(p.H), static_cast<const R*>(p.R),
-                         static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
-                         reinterpret_cast<unsigned*>(ws), L.ctrl_words, p.nmodels, L.cst_stride);
+    with_items<ITI>(L.items[0], [&](auto cf) {
+      with_items<IT>(L.items[1], [&](auto cb) {
+        hipLaunchKernelGGL((k_prepare<N, M, R, decltype(cf)::value, decltype(cb)::value>),
+                           dim3((unsigned)prep_blocks), dim3(256), 0, st,
+                           static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                           static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                           static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
+                           reinterpret_cast<unsigned*>(ws), L.ctrl_words, p.nmodels,
+                           L.cst_stride);
+      });
     });
     if (p.batch)
       hipLaunchKernelGGL((k_batch_tiles<1024>), dim3(1), dim3(1024), 0, st, p.len, p.row, p.nseq,
@@ -115,9 +119,12 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
       if (op == OP_RTS)
         hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, cst, y,
                            (const R*)mf, (const R*)Pf, ms, Ps);
+      else if (generic)
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, false>), grid(1), dim3(B), 0, st, ba, cst,
+                           y, (const R*)mf, (const R*)Pf, ms, Ps);
       else
-        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, cst, y,
-                           (const R*)mf, (const R*)Pf, ms, Ps);
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, true>), grid(1), dim3(B), 0, st, ba, cst,
+                           y, (const R*)mf, (const R*)Pf, ms, Ps);
     });
   }
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;

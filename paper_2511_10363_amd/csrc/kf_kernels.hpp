@@ -42,6 +42,13 @@ template <int N, int M, int L = 1> struct CL {
                        P0 = m0 + N, SL = P0 + N * N, PHI = SL + 3 * N * N,
                        PSI = PHI + L * N * M, SIZE = PSI + L * N * M;
 };
+// A second set of aggregate tables, for the backward two-filter scan's L,
+// after the largest first set (kMaxItems steps).
+constexpr int kMaxItems = 16;
+template <int N, int M, int L> struct CLB {
+  static constexpr int SL = CL<N, M, kMaxItems>::SIZE, PHI = SL + 3 * N * N,
+                       PSI = PHI + L * N * M, SIZE = PSI + L * N * M;
+};
 
 // The preparation launch also zeroes the workspace's control region (tile
 // tickets, epochs, timeout flags, look-back status words and payloads) with a
@@ -58,14 +65,16 @@ template <int N, int M, int L = 1> struct CL {
 //   j <  h:  PHI_2h[j] = P1 PHI_h[j],              PSI_2h[j] = PSI_h[j] - P4 PHI_h[j]
 //   j >= h:  PHI_2h[j] = P2 PSI_h[j-h] + PHI_h[j-h], PSI_2h[j] = P3 PSI_h[j-h]
 // starting from S_1 = (A, C, J), PHI_1[0] = K, PSI_1[0] = W.
-template <int N, int M, class R, int L>
+template <int N, int M, class R, int L, int LB>
 __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const R* __restrict__ Q_,
                                                  const R* __restrict__ H_, const R* __restrict__ R_,
                                                  const R* __restrict__ m0_,
                                                  const R* __restrict__ P0_, R* __restrict__ cst,
                                                  unsigned* __restrict__ ctrl, size_t ctrl_words,
                                                  long nmodels, long cst_stride) {
-  static_assert((L & (L - 1)) == 0 && L <= 64, "aggregate length must be a power of two");
+  static_assert((L & (L - 1)) == 0 && (LB & (LB - 1)) == 0 && L <= kMaxItems && LB <= kMaxItems,
+                "aggregate lengths must be powers of two up to kMaxItems");
+  constexpr int LMAX = L > LB ? L : LB;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ctrl_words;
        i += (size_t)gridDim.x * blockDim.x)
     ctrl[i] = 0u;
@@ -84,7 +93,7 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   __shared__ MPart<N, D> sS[2];       // S_h, double-buffered
   __shared__ D sPc[4][N][N];          // P1..P4 of S_h (x) S_h
   __shared__ D sW[4][N][N];           // combine scratch
-  __shared__ D sPHI[2][L][N][M], sPSI[2][L][N][M];
+  __shared__ D sPHI[2][LMAX][N][M], sPSI[2][LMAX][N][M];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   auto load_model = [&](D (&F)[N][N], D (&Q)[N][N], D (&H)[M][N], D (&Rm)[M][M]) {
 #pragma unroll
@@ -216,12 +225,31 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
       for (int j = 0; j < M; ++j) cst[LY::Rm + i * M + j] = R(0.5 * (Rm[i][j] + Rm[j][i]));
     }
   }
-  // doubling, all in wavefront 0 (lanes synchronise among themselves)
+  // doubling, all in wavefront 0 (lanes synchronise among themselves); the
+  // tables of h consecutive elements are written out when h reaches L (first
+  // set) and LB (second set)
   if (tid >= WAVE) return;
   wave_lds_sync();
+  auto write_set = [&](int cur, int h, int sl, int phi, int psi) {
+    if (lane < h) {
+#pragma unroll
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          cst[phi + lane * N * M + r * M + c] = R(sPHI[cur][lane][r][c]);
+          cst[psi + lane * N * M + r * M + c] = R(sPSI[cur][lane][r][c]);
+        }
+    }
+    if (lane < N * N) {
+      const int r = lane / N, c = lane % N;
+      cst[sl + r * N + c] = R(sS[cur].A[r][c]);
+      cst[sl + N * N + r * N + c] = R(sS[cur].C[r][c]);
+      cst[sl + 2 * N * N + r * N + c] = R(sS[cur].J[r][c]);
+    }
+  };
   int cur = 0;
 #pragma unroll 1
-  for (int h = 1; h < L; h *= 2) {
+  for (int h = 1; h < LMAX; h *= 2) {
     mpart_combine_lanes<N, D>(sS[cur], sS[cur], sS[cur ^ 1], sPc, sW, lane);
     const int j = lane;
     if (j < 2 * h) {
@@ -248,22 +276,11 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     }
     wave_lds_sync();
     cur ^= 1;
+    if (2 * h == L) write_set(cur, L, LY::SL, LY::PHI, LY::PSI);
+    if (2 * h == LB) write_set(cur, LB, CLB<N, M, LB>::SL, CLB<N, M, LB>::PHI, CLB<N, M, LB>::PSI);
   }
-  if (lane < L) {
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        cst[LY::PHI + lane * N * M + r * M + c] = R(sPHI[cur][lane][r][c]);
-        cst[LY::PSI + lane * N * M + r * M + c] = R(sPSI[cur][lane][r][c]);
-      }
-  }
-  if (lane < N * N) {
-    const int r = lane / N, c = lane % N;
-    cst[LY::SL + r * N + c] = R(sS[cur].A[r][c]);
-    cst[LY::SL + N * N + r * N + c] = R(sS[cur].C[r][c]);
-    cst[LY::SL + 2 * N * N + r * N + c] = R(sS[cur].J[r][c]);
-  }
+  if (L == 1) write_set(cur, 1, LY::SL, LY::PHI, LY::PSI);
+  if (LB == 1) write_set(cur, 1, CLB<N, M, LB>::SL, CLB<N, M, LB>::PHI, CLB<N, M, LB>::PSI);
 }
 
 // Output stores are plain (write-back) stores: the L2 merges the 16-byte
@@ -1148,7 +1165,7 @@ __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a,
 // J_{k+1|k+2:T}.  The anchored state is that (eta, J); the combination with
 // the filter result (m_in, P_in) is fused into the step phase.
 // ---------------------------------------------------------------------------
-template <int N, int M, class P, int L> struct TwoFilterPipe {
+template <int N, int M, class P, int L, bool TI> struct TwoFilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
   const ScanArgs<R>& a;
@@ -1179,7 +1196,40 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
     for (int c = 0; c < M; ++c) yk[c] = (k >= 0 && k + 1 < T) ? y[(k + 1) * M + c] : R(0);
   }
   KF_DEV E element(long k, const R (&yk)[M]) const { return tf_element<N, M, R>(cst, T, k, yk); }
+  // With TI, a thread whose rows all hold generic elements (no row T-1) folds
+  // them as the time-invariant filter does: the aggregate of L consecutive
+  // generic elements has the matrix part SL and the vector part
+  // b = sum_i PHI[i] y_i, eta = sum_i PSI[i] y_i (second table set, for this L).
   KF_DEV E fold() const {
+    if (TI && k0 + L - 1 <= T - 2) {
+      using LY = CLB<N, M, L>;
+      R yv[L][M];
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c) yv[i][c] = y[(k0 + 1 + i) * M + c];
+      E e;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        R b = R(0), h = R(0);
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+          for (int q = 0; q < M; ++q) {
+            b += cst[LY::PHI + i * N * M + r * M + q] * yv[i][q];
+            h += cst[LY::PSI + i * N * M + r * M + q] * yv[i][q];
+          }
+        e.b[r] = b;
+        e.e[r] = h;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          e.A[r][j] = cst[LY::SL + r * N + j];
+          e.C[r][j] = cst[LY::SL + N * N + r * N + j];
+          e.J[r][j] = cst[LY::SL + 2 * N * N + r * N + j];
+        }
+      }
+      return e;
+    }
     E agg;
     set_identity(agg);
     R yn[M];
@@ -1241,12 +1291,12 @@ template <int N, int M, class P, int L> struct TwoFilterPipe {
   }
 };
 
-template <int N, int M, class P, int BLOCK, int L>
+template <int N, int M, class P, int BLOCK, int L, bool TI>
 __global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a,
                                                      KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  TwoFilterPipe<N, M, P, L> pp(a, io);
-  scan_tile<TwoFilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+  TwoFilterPipe<N, M, P, L, TI> pp(a, io);
+  scan_tile<TwoFilterPipe<N, M, P, L, TI>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 }  // namespace kfs

@@ -144,8 +144,9 @@ inline Layout make_layout(const Job& j) {
     // a ragged batch: sum over sequences of ceil(T_i / tile) <= nseq + total / tile
     L.grid[s] = j.batch ? nseq + ntiles_for(j.total_steps, L.items[s]) : L.ntiles[s] * nseq;
   }
-  const size_t cst_words =                               // CL<N, M, L>::SIZE
-      10 * n * n + 4 * n * m + m * m + 2 * n + 2 * (size_t)items_ti(j.nx) * n * m;
+  // CLB<N, M, L>::SIZE: the model quantities and two sets of aggregate tables
+  const size_t cst_words = 10 * n * n + 4 * n * m + m * m + 2 * n + 2 * 16 * (size_t)(n * m) +
+                           3 * n * n + 2 * 16 * (size_t)(n * m);
   L.cst_stride = (long)((cst_words + 63) & ~size_t(63));
   const size_t elem_words = 3 * n * n + 2 * n;           // largest element (filtering)
   const size_t pre_words = n + n * n;
