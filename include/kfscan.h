@@ -126,6 +126,27 @@ typedef struct kf_batch {
     void *m_smooth, *P_smooth;             /* device, smoothers only                 */
 } kf_batch;
 
+/* A time-varying model with inputs (Sec. III-A with u, d; the model of the
+ * paper's experiments, Sec. VI-A), shared by nseq sequences of T steps.  Row j
+ * of the per-step arrays belongs to step j+1 (j = 0 .. T-1):
+ *   F, Q [T][nx][nx]   F_j, Q_j: x_{j+1} = F_j x_j + u_j + q_j, q_j ~ N(0, Q_j)
+ *   u    [T][nx]       u_j, or NULL for zero inputs
+ *   H, R [T][ny][nx], [T][ny][ny]   H_{j+1}, R_{j+1}: y_{j+1} = H x_{j+1} + d + r
+ *   d    [T][ny]       d_{j+1}, or NULL for zero offsets
+ * The elements are built step by step from these arrays (eqs. pkf_init1..3,
+ * prts_init1..2 with u, d) and scanned with the look-back scans over full
+ * elements; the one-kernel-per-level scans are not offered (KF_ERR_UNSUPPORTED). */
+typedef struct kf_tv_problem {
+    int32_t nx, ny, precision, scan;       /* scan: KF_SCAN_AUTO, _LOOKBACK, _LOOKBACK_GENERIC */
+    int64_t T;                             /* steps per sequence, >= 1          */
+    int64_t nseq;                          /* sequences sharing the model, >= 1 */
+    const void *F, *Q, *H, *R, *u, *d;     /* per-step model, device            */
+    const void *m0, *P0;                   /* prior x_{0|0}, P_{0|0}, device    */
+    const void *y;                         /* [nseq][T][ny], device             */
+    void *m_filt, *P_filt;                 /* [nseq][T][nx], [nseq][T][nx][nx]  */
+    void *m_smooth, *P_smooth;             /* smoothers only                    */
+} kf_tv_problem;
+
 /* ABI version (KFSCAN_ABI_VERSION). */
 int kf_abi_version(void);
 
@@ -192,6 +213,15 @@ kf_status kf_smooth_rts_batch(const kf_batch *b, void *workspace, size_t workspa
                               void *stream);
 kf_status kf_smooth_twofilter_batch(const kf_batch *b, void *workspace, size_t workspace_bytes,
                                     void *stream);
+
+/* ---- Time-varying models ----------------------------------------------- */
+kf_status kf_tv_workspace_size(const kf_tv_problem *p, size_t *bytes);
+kf_status kf_filter_tv(const kf_tv_problem *p, void *workspace, size_t workspace_bytes,
+                       void *stream);
+kf_status kf_smooth_rts_tv(const kf_tv_problem *p, void *workspace, size_t workspace_bytes,
+                           void *stream);
+kf_status kf_smooth_twofilter_tv(const kf_tv_problem *p, void *workspace,
+                                 size_t workspace_bytes, void *stream);
 
 /* ---- Stage entry points ------------------------------------------------
  * For callers that schedule or time the passes themselves.  Each enqueues

@@ -69,6 +69,16 @@ static kf_status check_batch(const kf_batch* b) {
   return check_layout(job_of(*b));
 }
 
+static kf_status check_tv(const kf_tv_problem* p) {
+  if (!p) return KF_ERR_INVALID_ARG;
+  if (p->T < 1 || p->nseq < 1) return KF_ERR_INVALID_ARG;
+  if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
+  kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
+  if (s != KF_OK) return s;
+  if (is_tree_scan(p->scan)) return KF_ERR_UNSUPPORTED;
+  return check_layout(job_of(*p));
+}
+
 static kf_status run_job(Op op, int stages, const Job& j, void* ws, size_t ws_bytes,
                          void* stream) {
   if ((stages & ST_PREPARE) && (!j.F || !j.Q || !j.H || !j.R || !j.m0 || !j.P0))
@@ -95,6 +105,12 @@ static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws
   kf_status s = check_sizes(p);
   if (s != KF_OK) return s;
   return run_job(op, stages, job_of(*p), ws, ws_bytes, stream);
+}
+
+static kf_status run_tv(Op op, const kf_tv_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  kf_status s = check_tv(p);
+  if (s != KF_OK) return s;
+  return run_job(op, ST_ALL, job_of(*p), ws, ws_bytes, stream);
 }
 
 static kf_status run_batch(Op op, const kf_batch* b, void* ws, size_t ws_bytes, void* stream) {
@@ -154,6 +170,27 @@ kf_status kf_batch_workspace_size(const kf_batch* b, size_t* bytes) {
   if (s != KF_OK) return s;
   *bytes = kfs::make_layout(kfs::job_of(*b)).total;
   return KF_OK;
+}
+
+kf_status kf_tv_workspace_size(const kf_tv_problem* p, size_t* bytes) {
+  if (!bytes) return KF_ERR_INVALID_ARG;
+  kf_status s = kfs::check_tv(p);
+  if (s != KF_OK) return s;
+  *bytes = kfs::make_layout(kfs::job_of(*p)).total;
+  return KF_OK;
+}
+
+kf_status kf_filter_tv(const kf_tv_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run_tv(kfs::OP_FILTER, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_smooth_rts_tv(const kf_tv_problem* p, void* ws, size_t ws_bytes, void* stream) {
+  return kfs::run_tv(kfs::OP_RTS, p, ws, ws_bytes, stream);
+}
+
+kf_status kf_smooth_twofilter_tv(const kf_tv_problem* p, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  return kfs::run_tv(kfs::OP_TWOFILTER, p, ws, ws_bytes, stream);
 }
 
 kf_status kf_workspace_clear(void* workspace, size_t bytes, void* stream) {

@@ -39,7 +39,16 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
   const long cst_stride = (p.batch && p.nmodels > 1) ? L.cst_stride : 0;
   // the aggregate tables are built for the forward scan's L (unused by the
   // generic scan, whose L only sizes them)
-  if (stages & ST_PREPARE) {
+  TvModel<R> tvm{};
+  if (p.tv) {
+    tvm = TvModel<R>{static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                     static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                     static_cast<const R*>(p.u), static_cast<const R*>(p.d),
+                     static_cast<const R*>(p.m0), static_cast<const R*>(p.P0)};
+    if (stages & ST_PREPARE)
+      hipLaunchKernelGGL((k_clear<256>), dim3((unsigned)prep_blocks), dim3(256), 0, st,
+                         reinterpret_cast<unsigned*>(ws), L.ctrl_words);
+  } else if (stages & ST_PREPARE) {
     with_items<ITI>(L.items[0], [&](auto cf) {
       with_items<IT>(L.items[1], [&](auto cb) {
         hipLaunchKernelGGL((k_prepare<N, M, R, decltype(cf)::value, decltype(cb)::value>),
@@ -101,10 +110,15 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
   auto grid = [&](int slot) { return dim3((unsigned)L.grid[slot]); };
   if (stages & ST_FORWARD) {
     ScanArgs<R> fa = args(0);
-    if (generic)
+    if (p.tv)
+      with_items<IT>(L.items[0], [&](auto c) {
+        hipLaunchKernelGGL((k_filter<N, M, P, B, decltype(c)::value, true>), grid(0), dim3(B), 0,
+                           st, fa, tvm, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
+      });
+    else if (generic)
       with_items<IT>(L.items[0], [&](auto c) {
         hipLaunchKernelGGL((k_filter<N, M, P, B, decltype(c)::value>), grid(0), dim3(B), 0, st,
-                           fa, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
+                           fa, tvm, cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
       });
     else
       with_items<ITI>(L.items[0], [&](auto c) {
@@ -116,15 +130,21 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
     ScanArgs<R> ba = args(1);
     with_items<IT>(L.items[1], [&](auto c) {
       constexpr int IL = decltype(c)::value;
-      if (op == OP_RTS)
-        hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, cst, y,
+      if (op == OP_RTS && p.tv)
+        hipLaunchKernelGGL((k_rts<N, M, P, B, IL, true>), grid(1), dim3(B), 0, st, ba, tvm, cst, y,
                            (const R*)mf, (const R*)Pf, ms, Ps);
+      else if (op == OP_RTS)
+        hipLaunchKernelGGL((k_rts<N, M, P, B, IL>), grid(1), dim3(B), 0, st, ba, tvm, cst, y,
+                           (const R*)mf, (const R*)Pf, ms, Ps);
+      else if (p.tv)
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, false, true>), grid(1), dim3(B), 0, st, ba,
+                           tvm, cst, y, (const R*)mf, (const R*)Pf, ms, Ps);
       else if (generic)
-        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, false>), grid(1), dim3(B), 0, st, ba, cst,
-                           y, (const R*)mf, (const R*)Pf, ms, Ps);
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, false>), grid(1), dim3(B), 0, st, ba, tvm,
+                           cst, y, (const R*)mf, (const R*)Pf, ms, Ps);
       else
-        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, true>), grid(1), dim3(B), 0, st, ba, cst,
-                           y, (const R*)mf, (const R*)Pf, ms, Ps);
+        hipLaunchKernelGGL((k_twofilter<N, M, P, B, IL, true>), grid(1), dim3(B), 0, st, ba, tvm,
+                           cst, y, (const R*)mf, (const R*)Pf, ms, Ps);
     });
   }
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;

@@ -289,6 +289,14 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
 // own, which costs several times more.
 template <class R> KF_DEV void st_out(R* p, R v) { *p = v; }
 
+// Zeroes the workspace's control region (in place of the preparation kernel
+// when there are no model constants to derive).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_clear(unsigned* __restrict__ ctrl, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)BLOCK + threadIdx.x; i < words; i += (size_t)gridDim.x * BLOCK)
+    ctrl[i] = 0u;
+}
+
 // Ragged batches: validate every sequence and lay out the tiles of both scan
 // slots, whose tiles hold tile0 and tile1 steps.  start[s][i] is the first
 // tile ticket of sequence i (start[s][nseq] the number of tiles), map[s][g]
@@ -444,6 +452,220 @@ KF_DEV FElem<N, R> filter_element(const R* __restrict__ cst, long k, const R (&y
     }
   }
   return a;
+}
+
+// ---------------------------------------------------------------------------
+// Time-varying models (u, d optional).  Row r of the per-step arrays holds
+// F_r, Q_r, u_r (the prediction into step r+1) and H_{r+1}, R_{r+1}, d_{r+1};
+// m0, P0 are the prior.  Shared by all sequences of a call.
+// ---------------------------------------------------------------------------
+template <class R> struct TvModel {
+  const R* F;
+  const R* Q;
+  const R* H;
+  const R* Rm;
+  const R* u;   // may be null (zero)
+  const R* d;   // may be null (zero)
+  const R* m0;
+  const R* P0;
+};
+
+template <int N, class R> KF_DEV void load_mat(const R* __restrict__ p, R (&A)[N][N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[i][j] = p[i * N + j];
+}
+
+// Filtering element of row r (step r+1) of a time-varying model: eqs.
+// pkf_init1 (r > 0) and pkf_init2 (r = 0) with the inputs u, d, and
+// eq. pkf_init3 for (eta, J) (reading C4 at r = 0), factorisations in P::S.
+template <int N, int M, class P>
+KF_DEV FElem<N, typename P::R> filter_element_tv(const TvModel<typename P::R>& tv, long r,
+                                                  const typename P::R (&yk)[M]) {
+  using R = typename P::R;
+  using S = typename P::S;
+  R F[N][N], Q[N][N], H[M][N], Rm[M][M], u[N], d[M];
+  load_mat<N, R>(tv.F + r * N * N, F);
+  load_mat<N, R>(tv.Q + r * N * N, Q);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) H[i][j] = tv.H[r * M * N + i * N + j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) Rm[i][j] = tv.Rm[r * M * M + i * M + j];
+    d[i] = tv.d ? tv.d[r * M + i] : R(0);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = tv.u ? tv.u[r * N + i] : R(0);
+  FElem<N, R> e;
+  // S = H Q H^T + R (the S of eq. pkf_init1), residual v = y - H u - d
+  S HQ[M][N], Sm[M][M], sd[M];
+  mm<M, N, N, S>(H, Q, HQ);
+  sym_xyt_plus<M, N, S>(HQ, H, Rm, Sm);
+  chol_factor<M, S>(Sm, sd);
+  S HF[M][N], B[M][N + 1];  // [S^{-1} H F | S^{-1} v]
+  mm<M, N, N, S>(H, F, HF);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    S v = S(yk[i]) - S(d[i]);
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      v -= S(H[i][t]) * S(u[t]);
+      B[i][t] = HF[i][t];
+    }
+    B[i][N] = v;
+  }
+  S vres[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) vres[i] = B[i][N];
+  chol_solve<M, N + 1, S>(Sm, sd, B);
+  // eta = (H F)^T S^{-1} v,  J = (H F)^T S^{-1} (H F)
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    S s = S(0);
+#pragma unroll
+    for (int t = 0; t < M; ++t) s += HF[t][i] * B[t][N];
+    e.e[i] = R(s);
+  }
+  S Jm[N][N], Z[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Z[i][j] = S(0);
+  {
+    S SiHF[M][N];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) SiHF[i][j] = B[i][j];
+    sym_xty_plus<N, M, S>(HF, SiHF, Z, Jm);
+  }
+  copy_mat<N, N, R>(Jm, e.J);
+  if (r > 0) {
+    S Kt[M][N];  // K^T = S^{-1} H Q
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Kt[i][j] = HQ[i][j];
+    chol_solve<M, N, S>(Sm, sd, Kt);
+    S IKH[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        S s = (i == j) ? S(1) : S(0);
+#pragma unroll
+        for (int t = 0; t < M; ++t) s -= Kt[t][i] * S(H[t][j]);
+        IKH[i][j] = s;
+      }
+    S A[N][N], C[N][N];
+    mm<N, N, N, S>(IKH, F, A);
+    mm<N, N, N, S>(IKH, Q, C);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      S s = S(u[i]);  // b = u + K v
+#pragma unroll
+      for (int t = 0; t < M; ++t) s += Kt[t][i] * vres[t];
+      e.b[i] = R(s);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        e.A[i][j] = R(A[i][j]);
+        e.C[i][j] = R(S(0.5) * (C[i][j] + C[j][i]));
+      }
+    }
+  } else {
+    // eq. pkf_init2: predict the prior, then condition on y_1
+    R m0[N], P0[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) m0[i] = tv.m0[i];
+    load_mat<N, R>(tv.P0, P0);
+    S xp[N], FP[N][N], Pp[N][N];
+    mv<N, N, S>(F, m0, xp);
+#pragma unroll
+    for (int i = 0; i < N; ++i) xp[i] += S(u[i]);
+    mm<N, N, N, S>(F, P0, FP);
+    sym_xyt_plus<N, N, S>(FP, F, Q, Pp);
+    S HP[M][N + 1], S1[M][M], s1d[M];
+    {
+      S HPm[M][N];
+      mm<M, N, N, S>(H, Pp, HPm);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        S v = S(yk[i]) - S(d[i]);
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          v -= S(H[i][t]) * xp[t];
+          HP[i][t] = HPm[i][t];
+        }
+        HP[i][N] = v;
+      }
+      sym_xyt_plus<M, N, S>(HPm, H, Rm, S1);
+    }
+    chol_factor<M, S>(S1, s1d);
+    S K1[M][N + 1];  // [S1^{-1} H Pp | S1^{-1} v1]
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = 0; j <= N; ++j) K1[i][j] = HP[i][j];
+    chol_solve<M, N + 1, S>(S1, s1d, K1);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      S s = xp[i];
+#pragma unroll
+      for (int t = 0; t < M; ++t) s += HP[t][i] * K1[t][N];
+      e.b[i] = R(s);
+#pragma unroll
+      for (int j = 0; j < N; ++j) e.A[i][j] = R(0);
+    }
+    // C_1 = Pp - (H Pp)^T S1^{-1} (H Pp), upper triangle mirrored
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        S s = Pp[i][j];
+#pragma unroll
+        for (int t = 0; t < M; ++t) s -= HP[t][i] * K1[t][j];
+        e.C[i][j] = R(s);
+        e.C[j][i] = R(s);
+      }
+  }
+  return e;
+}
+
+// Smoothing element of row k of a time-varying model (eq. prts_init1 with
+// F_{k+1}, Q_{k+1}, u_{k+1}: g = x - E (F x + u)); eq. prts_init2 at the last row.
+template <int N, class P>
+KF_DEV SElem<N, typename P::R> rts_element_tv(const TvModel<typename P::R>& tv, long T, long k,
+                                              const typename P::R (&x)[N],
+                                              const typename P::R (&Pk)[N][N]) {
+  using R = typename P::R;
+  SElem<N, R> e;
+  if (k == T - 1) {
+    set_identity(e);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      e.E[i][i] = R(0);
+      e.g[i] = x[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) e.L[i][j] = Pk[i][j];
+    }
+    return e;
+  }
+  R F[N][N], Q[N][N];
+  load_mat<N, R>(tv.F + (k + 1) * N * N, F);
+  load_mat<N, R>(tv.Q + (k + 1) * N * N, Q);
+  e = smooth_element<N, P>(x, Pk, F, Q);
+  if (tv.u) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int t = 0; t < N; ++t) s += e.E[i][t] * tv.u[(k + 1) * N + t];
+      e.g[i] -= s;
+    }
+  }
+  return e;
 }
 
 // The last block of a pass to finish resets the tile ticket and the finished
@@ -689,7 +911,7 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
 // Forward filter (Algorithm 5): elements (eqs. pkf_init1..3), Lemma 1,
 // anchored state (x_{k|k}, P_{k|k}) = (b, C) of a prefix that holds step 1.
 // ---------------------------------------------------------------------------
-template <int N, int M, class P, int L> struct FilterPipe {
+template <int N, int M, class P, int L, bool TV = false> struct FilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
   const ScanArgs<R>& a;
@@ -699,7 +921,13 @@ template <int N, int M, class P, int L> struct FilterPipe {
   const R* __restrict__ y;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV FilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
+  const TvModel<R> tvm;
+  KF_DEV FilterPipe(const ScanArgs<R>& a_, const IO<R>& io_, const TvModel<R>& tv_)
+      : a(a_), io(io_), tvm(tv_) {}
+  KF_DEV E element(long k, const R (&yk)[M]) const {
+    if constexpr (TV) return filter_element_tv<N, M, P>(tvm, k, yk);
+    else return filter_element<N, M, R>(cst, k, yk);
+  }
   KF_DEV void bind(const SeqInfo& s, long t, int tid) {
     T = s.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
@@ -726,7 +954,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      E el = filter_element<N, M, R>(cst, k, yk);
+      E el = element(k, yk);
       agg = (i == 0) ? el : fcombine<N, P>(agg, el);
     }
     return agg;
@@ -757,7 +985,7 @@ template <int N, int M, class P, int L> struct FilterPipe {
       R yk[M];
       copy_vec<M, R>(yn, yk);
       load_y(k + 1, yn);
-      fapply<N, P>(st.v, st.m, filter_element<N, M, R>(cst, k, yk));
+      fapply<N, P>(st.v, st.m, element(k, yk));
       st_store_out(k, st);
     }
   }
@@ -776,12 +1004,13 @@ template <int N, int M, class P, int L> struct FilterPipe {
       const R* __restrict__ P_in, R* __restrict__ m_out, R* __restrict__ P_out
 #define KFS_IO_MAKE(R) const IO<R> io{cst, y, m_in, P_in, m_out, P_out}
 
-template <int N, int M, class P, int BLOCK, int L>
+template <int N, int M, class P, int BLOCK, int L, bool TV = false>
 __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a,
+                                                  TvModel<typename P::R> tv,
                                                   KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  FilterPipe<N, M, P, L> pp(a, io);
-  scan_tile<FilterPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+  FilterPipe<N, M, P, L, TV> pp(a, io, tv);
+  scan_tile<FilterPipe<N, M, P, L, TV>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -987,7 +1216,7 @@ KF_DEV FElem<N, R> tf_element(const R* __restrict__ cst, long T, long k, const R
   return e;
 }
 
-template <int N, int M, class P, int L, int B> struct RtsPipe {
+template <int N, int M, class P, int L, int B, bool TV = false> struct RtsPipe {
   using R = typename P::R;
   using E = SElem<N, R>;
   using LY = CL<N, M>;
@@ -999,7 +1228,9 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV RtsPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
+  const TvModel<R> tvm;
+  KF_DEV RtsPipe(const ScanArgs<R>& a_, const IO<R>& io_, const TvModel<R>& tv_)
+      : a(a_), io(io_), tvm(tv_) {}
   KF_DEV void bind(const SeqInfo& s, long t, int tid) {
     T = s.T;
     const long tt = s.ntiles - 1 - t;
@@ -1016,7 +1247,8 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
     if (k >= 0 && k < T) load_state<N, R>(mf, Pf, k, x, Pk);
   }
   KF_DEV E element(long k, const R (&x)[N], const R (&Pk)[N][N]) const {
-    return rts_element<N, M, P>(cst, T, k, x, Pk);
+    if constexpr (TV) return rts_element_tv<N, P>(tvm, T, k, x, Pk);
+    else return rts_element<N, M, P>(cst, T, k, x, Pk);
   }
   // Steps are walked last to first in groups of PG consecutive rows whose
   // covariances fill one 128-byte line (two rows at nx = 4 in FP32), with the
@@ -1149,12 +1381,12 @@ template <int N, int M, class P, int L, int B> struct RtsPipe {
   }
 };
 
-template <int N, int M, class P, int BLOCK, int L>
-__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a,
+template <int N, int M, class P, int BLOCK, int L, bool TV = false>
+__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a, TvModel<typename P::R> tv,
                                                KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  RtsPipe<N, M, P, L, BLOCK> pp(a, io);
-  scan_tile<RtsPipe<N, M, P, L, BLOCK>, N, typename P::R, BLOCK, L>(pp, a);
+  RtsPipe<N, M, P, L, BLOCK, TV> pp(a, io, tv);
+  scan_tile<RtsPipe<N, M, P, L, BLOCK, TV>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,7 +1397,7 @@ __global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a,
 // J_{k+1|k+2:T}.  The anchored state is that (eta, J); the combination with
 // the filter result (m_in, P_in) is fused into the step phase.
 // ---------------------------------------------------------------------------
-template <int N, int M, class P, int L, bool TI> struct TwoFilterPipe {
+template <int N, int M, class P, int L, bool TI, bool TV = false> struct TwoFilterPipe {
   using R = typename P::R;
   using E = FElem<N, R>;
   const ScanArgs<R>& a;
@@ -1177,7 +1409,9 @@ template <int N, int M, class P, int L, bool TI> struct TwoFilterPipe {
   const R* __restrict__ Pf;
   R* __restrict__ mo;
   R* __restrict__ Po;
-  KF_DEV TwoFilterPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
+  const TvModel<R> tvm;
+  KF_DEV TwoFilterPipe(const ScanArgs<R>& a_, const IO<R>& io_, const TvModel<R>& tv_)
+      : a(a_), io(io_), tvm(tv_) {}
   KF_DEV void bind(const SeqInfo& s, long t, int tid) {
     T = s.T;
     const long tt = s.ntiles - 1 - t;
@@ -1195,13 +1429,22 @@ template <int N, int M, class P, int L, bool TI> struct TwoFilterPipe {
 #pragma unroll
     for (int c = 0; c < M; ++c) yk[c] = (k >= 0 && k + 1 < T) ? y[(k + 1) * M + c] : R(0);
   }
-  KF_DEV E element(long k, const R (&yk)[M]) const { return tf_element<N, M, R>(cst, T, k, yk); }
+  KF_DEV E element(long k, const R (&yk)[M]) const {
+    if constexpr (TV) {
+      E e;
+      if (k == T - 1) set_identity(e);
+      else e = filter_element_tv<N, M, P>(tvm, k + 1, yk);
+      return e;
+    } else {
+      return tf_element<N, M, R>(cst, T, k, yk);
+    }
+  }
   // With TI, a thread whose rows all hold generic elements (no row T-1) folds
   // them as the time-invariant filter does: the aggregate of L consecutive
   // generic elements has the matrix part SL and the vector part
   // b = sum_i PHI[i] y_i, eta = sum_i PSI[i] y_i (second table set, for this L).
   KF_DEV E fold() const {
-    if (TI && k0 + L - 1 <= T - 2) {
+    if (TI && !TV && k0 + L - 1 <= T - 2) {
       using LY = CLB<N, M, L>;
       R yv[L][M];
 #pragma unroll
@@ -1291,12 +1534,13 @@ template <int N, int M, class P, int L, bool TI> struct TwoFilterPipe {
   }
 };
 
-template <int N, int M, class P, int BLOCK, int L, bool TI>
+template <int N, int M, class P, int BLOCK, int L, bool TI, bool TV = false>
 __global__ __launch_bounds__(BLOCK) void k_twofilter(ScanArgs<typename P::R> a,
+                                                     TvModel<typename P::R> tv,
                                                      KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  TwoFilterPipe<N, M, P, L, TI> pp(a, io);
-  scan_tile<TwoFilterPipe<N, M, P, L, TI>, N, typename P::R, BLOCK, L>(pp, a);
+  TwoFilterPipe<N, M, P, L, TI, TV> pp(a, io, tv);
+  scan_tile<TwoFilterPipe<N, M, P, L, TI, TV>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 }  // namespace kfs

@@ -75,6 +75,8 @@ struct Job {
   const int64_t* row;         // ragged batch, device [nseq]
   const void *F, *Q, *H, *R, *m0, *P0, *y;
   void *m_filt, *P_filt, *m_smooth, *P_smooth;
+  bool tv;                    // F, Q, H, R, u, d are per-step arrays
+  const void *u, *d;          // time-varying model: may be null
 };
 
 inline Job job_of(const kf_problem& p) {
@@ -89,6 +91,26 @@ inline Job job_of(const kf_problem& p) {
   j.nmodels = 1;
   j.total_steps = p.T * p.nseq;
   j.F = p.F; j.Q = p.Q; j.H = p.H; j.R = p.R; j.m0 = p.m0; j.P0 = p.P0;
+  j.y = p.y;
+  j.m_filt = p.m_filt; j.P_filt = p.P_filt; j.m_smooth = p.m_smooth; j.P_smooth = p.P_smooth;
+  return j;
+}
+
+inline Job job_of(const kf_tv_problem& p) {
+  Job j{};
+  j.nx = p.nx;
+  j.ny = p.ny;
+  j.precision = p.precision;
+  // the per-step elements are folded by the look-back scans over full elements
+  j.scan = KF_SCAN_LOOKBACK_GENERIC;
+  j.T = p.T;
+  j.nseq = p.nseq;
+  j.batch = false;
+  j.nmodels = 1;
+  j.total_steps = p.T * p.nseq;
+  j.F = p.F; j.Q = p.Q; j.H = p.H; j.R = p.R; j.m0 = p.m0; j.P0 = p.P0;
+  j.u = p.u; j.d = p.d;
+  j.tv = true;
   j.y = p.y;
   j.m_filt = p.m_filt; j.P_filt = p.P_filt; j.m_smooth = p.m_smooth; j.P_smooth = p.P_smooth;
   return j;

@@ -51,6 +51,16 @@ class KfBatch(ctypes.Structure):
                 ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
 
 
+class KfTvProblem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("scan", ctypes.c_int32),
+                ("T", ctypes.c_int64), ("nseq", ctypes.c_int64),
+                ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
+                ("u", _VOIDP), ("d", _VOIDP), ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
+                ("m_filt", _VOIDP), ("P_filt", _VOIDP),
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+
+
 class KfScanError(RuntimeError):
     pass
 
@@ -61,7 +71,8 @@ EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_s
            "kf_workspace_clear", "kf_workspace_timed_out", "kf_device_copy", "kf_filter", "kf_smooth_rts",
            "kf_smooth_twofilter", "kf_prepare", "kf_pass_filter", "kf_pass_rts",
            "kf_pass_twofilter", "kf_batch_workspace_size", "kf_filter_batch",
-           "kf_smooth_rts_batch", "kf_smooth_twofilter_batch", "kf_workspace_status")
+           "kf_smooth_rts_batch", "kf_smooth_twofilter_batch", "kf_workspace_status",
+           "kf_tv_workspace_size", "kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv")
 STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
 # When set (the tests set it), every call synchronises and checks the
 # workspace's look-back timeout flag.
@@ -93,6 +104,12 @@ def load_library(path: str = LIB_PATH):
         for name in ("kf_filter_batch", "kf_smooth_rts_batch", "kf_smooth_twofilter_batch"):
             getattr(lib, name).restype = ctypes.c_int
             getattr(lib, name).argtypes = [B, _VOIDP, ctypes.c_size_t, _VOIDP]
+        V = ctypes.POINTER(KfTvProblem)
+        lib.kf_tv_workspace_size.restype = ctypes.c_int
+        lib.kf_tv_workspace_size.argtypes = [V, ctypes.POINTER(ctypes.c_size_t)]
+        for name in ("kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv"):
+            getattr(lib, name).restype = ctypes.c_int
+            getattr(lib, name).argtypes = [V, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_workspace_status.restype = ctypes.c_int
         lib.kf_workspace_status.argtypes = [_VOIDP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32),
                                             _VOIDP]
@@ -343,6 +360,62 @@ def batch(entry, models, y, T, offset, precision="f32", scan="auto", workspace=N
     if entry != "filter":
         outs += (keep["m_smooth"], keep["P_smooth"])
     return outs, ws
+
+
+def tv(entry, F, Q, H, R, u, d, m0, P0, y, precision="f32", scan="auto", workspace=None):
+    """A time-varying model (kf_*_tv): F, Q [T, nx, nx], H [T, ny, nx], R [T, ny, ny],
+    u [T, nx] or None, d [T, ny] or None (row j belongs to step j+1), prior m0,
+    P0, measurements y [T, ny] or [nseq, T, ny].  entry is "filter", "rts" or
+    "tf".  Returns (x_{k|k}, P_{k|k}[, x_{k|T}, P_{k|T}])."""
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be one of %s" % list(PRECISIONS))
+    dt = dtype_for(precision)
+    was2d = y.dim() == 2
+    yy = y.unsqueeze(0) if was2d else y
+    nseq, T, ny = yy.shape
+    nx = F.shape[-1]
+    dev = y.device
+    if dev.type != "cuda":
+        raise KfScanError("kfscan runs on the GPU only; y is on %s" % dev)
+    shapes = {"F": (F, (T, nx, nx)), "Q": (Q, (T, nx, nx)), "H": (H, (T, ny, nx)),
+              "R": (R, (T, ny, ny)), "m0": (m0, (nx,)), "P0": (P0, (nx, nx))}
+    if u is not None:
+        shapes["u"] = (u, (T, nx))
+    if d is not None:
+        shapes["d"] = (d, (T, ny))
+    for name, (t, shp) in shapes.items():
+        if tuple(t.shape) != shp:
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shp))
+        if t.device != dev or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor on %s" % (name, dt, dev))
+    if yy.dtype != dt or not yy.is_contiguous():
+        raise ValueError("y must be a contiguous %s tensor" % dt)
+    outs = [torch.empty((nseq, T, nx), dtype=dt, device=dev),
+            torch.empty((nseq, T, nx, nx), dtype=dt, device=dev)]
+    if entry != "filter":
+        outs += [torch.empty((nseq, T, nx), dtype=dt, device=dev),
+                 torch.empty((nseq, T, nx, nx), dtype=dt, device=dev)]
+    p = KfTvProblem()
+    p.nx, p.ny, p.precision, p.scan = nx, ny, PRECISIONS[precision], SCANS[scan]
+    p.T, p.nseq = T, nseq
+    p.F, p.Q, p.H, p.R = F.data_ptr(), Q.data_ptr(), H.data_ptr(), R.data_ptr()
+    p.u = u.data_ptr() if u is not None else None
+    p.d = d.data_ptr() if d is not None else None
+    p.m0, p.P0, p.y = m0.data_ptr(), P0.data_ptr(), yy.data_ptr()
+    p.m_filt, p.P_filt = outs[0].data_ptr(), outs[1].data_ptr()
+    if entry != "filter":
+        p.m_smooth, p.P_smooth = outs[2].data_ptr(), outs[3].data_ptr()
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.kf_tv_workspace_size(ctypes.byref(p), ctypes.byref(n)), "kf_tv_workspace_size")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ws = workspace if workspace is not None else Workspace.get(dev, stream, n.value)
+    nbytes = ws.numel() * ws.element_size()
+    name = {"filter": "kf_filter_tv", "rts": "kf_smooth_rts_tv", "tf": "kf_smooth_twofilter_tv"}[entry]
+    _check(getattr(lib, name)(ctypes.byref(p), ws.data_ptr(), nbytes, stream), name)
+    if CHECK and workspace_status(ws) & 1:
+        raise KfScanError("%s: a look-back wait timed out; outputs are invalid" % name)
+    return tuple(_squeeze(o, was2d) for o in outs)
 
 
 class Plan:

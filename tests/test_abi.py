@@ -124,3 +124,22 @@ def test_batch_entry_points_reject_before_launch(kfscan):
     assert lib.kf_filter_batch(ctypes.byref(b), None, 0, None) == 3      # no workspace
     status = ctypes.c_uint32(0)
     assert lib.kf_workspace_status(None, 0, ctypes.byref(status), None) == 3
+
+
+def test_tv_workspace_size_and_validation(kfscan):
+    lib = kfscan.load_library()
+    n = ctypes.c_size_t(0)
+
+    def tvp(**kw):
+        p = kfscan.KfTvProblem()
+        p.nx, p.ny, p.precision, p.scan = kw.get("nx", 4), 2, kw.get("prec", 1), kw.get("scan", 0)
+        p.T, p.nseq = kw.get("T", 1 << 16), kw.get("nseq", 1)
+        return p
+    size = lambda p: lib.kf_tv_workspace_size(ctypes.byref(p), ctypes.byref(n))  # noqa: E731
+    assert size(tvp()) == 0 and n.value > 0
+    assert size(tvp(T=0)) == 1
+    assert size(tvp(nx=5)) == 2
+    assert size(tvp(scan=3)) == 2          # tree scans are not offered for time-varying models
+    p = tvp(T=100)
+    for name in ("kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv"):
+        assert getattr(lib, name)(ctypes.byref(p), None, 0, None) == 1   # null pointers
