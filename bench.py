@@ -83,10 +83,12 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
-    ap.add_argument("--workload", default="tracking", choices=["tracking", "batched", "serving"],
+    ap.add_argument("--workload", default="tracking",
+                    choices=["tracking", "batched", "serving", "tv"],
                     help="tracking: one long sequence (the headline); batched: 4096 ragged "
                          "sequences, a random stable model each; serving: Poisson job "
-                         "arrivals served in ragged batches")
+                         "arrivals served in ragged batches; tv: the paper's time-varying "
+                         "model with inputs")
     ap.add_argument("--jobs", type=int, default=2000, help="jobs of the serving workload")
     ap.add_argument("--nseq", type=int, default=4096, help="sequences of the batched workload")
     args = ap.parse_args()
@@ -109,6 +111,8 @@ def main() -> int:
         return bench_batched(args, np, torch, W, kfscan, dev)
     if args.workload == "serving":
         return bench_serving(args, np, torch, W, kfscan, dev)
+    if args.workload == "tv":
+        return bench_tv(args, np, torch, W, kfscan, dev)
     T = args.T if args.T > 0 else 1 << args.log2T
     tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
@@ -497,6 +501,92 @@ def bench_serving(args, np, torch, W, kfscan, dev) -> int:
                    "total_steps": total, "max_batch": max_batch, "seed": args.seed},
         "saturated_jobs_per_s": sat_jobs,
         "poisson": results,
+        "errors_vs_oracle": errors,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_tv(args, np, torch, W, kfscan, dev) -> int:
+    """The paper's time-varying model (Sec. VI-A): per step F_k = 0.99 x an
+    orthogonal factor, random SPD Q_k, R_k, Gaussian H_k, u_k, d_k; nx = 4,
+    ny = 2; filter + RTS smoother (kf_smooth_rts_tv), T = 2^log2T.  The
+    per-step model is streamed from HBM: algorithmic bytes per step are
+    w (m + 2n^2 + mn + m^2 + n + m + 2n + 2n^2) (y, the step's model, both
+    output pairs); the RTS pass reads F, Q, u again, which counts against."""
+    prec = args.precision
+    dt = kfscan.dtype_for(prec)
+    w = 8 if prec == "f64" else 4
+    T = args.T if args.T > 0 else 1 << args.log2T
+    n, m = 4, 2
+    rng = np.random.default_rng(args.seed)
+    model = W.paper_tv_model(T, rng, n, m)
+    y = W.simulate(model, T, rng)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt).contiguous()  # noqa: E731
+    F, Q, H, R, u, d = (dv(a) for a in (model.F, model.Q, model.H, model.R, model.u, model.d))
+    m0, P0, yd = dv(model.m0), dv(model.P0), dv(y)
+    ws = [None]
+
+    def one_pass():
+        outs = kfscan.tv("rts", F, Q, H, R, u, d, m0, P0, yd, precision=prec, workspace=ws[0])
+        return outs
+
+    outs = one_pass()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    K = args.steps
+    every = max(1, args.event_every)
+    evs = []
+    t0 = time.perf_counter()
+    for i in range(K):
+        if i % every == 0:
+            e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            e[0].record()
+            outs = one_pass()
+            e[1].record()
+            evs.append(e)
+        else:
+            outs = one_pass()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = T * K / wall
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    step_bytes = w * (m + 2 * n * n + m * n + m * m + n + m + 2 * n + 2 * n * n)
+    achieved = T * step_bytes / (lat.mean() * 1e-3) / 1e9
+    cpu = errors = None
+    if args.cpu_seconds > 0:
+        import oracle
+        cast = (lambda a: a) if prec == "f64" else (
+            lambda a: np.asarray(a, dtype=np.float32).astype(np.float64))
+        arrs = [cast(a) for a in (model.F, model.Q, model.H, model.R, model.m0, model.P0)]
+        reps = 0
+        c0 = time.perf_counter()
+        while True:
+            ref = oracle.smooth_rts(*arrs, cast(y), cast(model.u), cast(model.d))
+            reps += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        cpu = {"value": T * reps / (time.perf_counter() - c0), "unit": "steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "sequential FP64 filter + RTS smoother, time-varying model, T=%d, "
+                         "%d repetition(s)" % (T, reps)}
+        got = [o.double().cpu().numpy() for o in outs]
+        errors = {name: float(np.max(np.abs(g - r)) / np.max(np.abs(r)))
+                  for name, g, r in zip(("m_filt", "P_filt", "m_smooth", "P_smooth"), got, ref)}
+    out = {
+        "metric": "time-varying filter+smoother steps/s (the paper's model, nx=4, ny=2)",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "paper_tv_nx4_ny2_T%d" % T, "T": T, "inputs": "u, d",
+                   "pipeline": "kf_smooth_rts_tv", "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole pass"},
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))
