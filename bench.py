@@ -84,11 +84,12 @@ def main() -> int:
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
     ap.add_argument("--workload", default="tracking",
-                    choices=["tracking", "batched", "serving", "tv"],
+                    choices=["tracking", "batched", "serving", "tv", "speedup"],
                     help="tracking: one long sequence (the headline); batched: 4096 ragged "
                          "sequences, a random stable model each; serving: Poisson job "
                          "arrivals served in ragged batches; tv: the paper's time-varying "
-                         "model with inputs")
+                         "model with inputs; speedup: the parallel filter against the "
+                         "sequential filter on one GPU lane, over a range of T")
     ap.add_argument("--jobs", type=int, default=2000, help="jobs of the serving workload")
     ap.add_argument("--nseq", type=int, default=4096, help="sequences of the batched workload")
     args = ap.parse_args()
@@ -113,6 +114,8 @@ def main() -> int:
         return bench_serving(args, np, torch, W, kfscan, dev)
     if args.workload == "tv":
         return bench_tv(args, np, torch, W, kfscan, dev)
+    if args.workload == "speedup":
+        return bench_speedup(args, np, torch, W, kfscan, dev)
     T = args.T if args.T > 0 else 1 << args.log2T
     tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
@@ -588,6 +591,69 @@ def bench_tv(args, np, torch, W, kfscan, dev) -> int:
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "errors_vs_oracle": errors,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_speedup(args, np, torch, W, kfscan, dev) -> int:
+    """The speedup experiment of Sec. VI (GPU speedup analysis): the parallel
+    Kalman filter (Algorithm 5, look-back scan over full elements) against the
+    classical sequential filter run by one GPU lane (KF_SCAN_SEQUENTIAL), FP32,
+    on the paper's time-varying model (nx = 4, ny = 2, inputs u, d), for
+    T = 10^2 .. 10^6 and 2^20.  Both are timed with events around the one-call
+    entry point kf_filter_tv (the sequential one once per length after a
+    warm-up call, the parallel one as the median of --steps calls).  The model
+    and measurements are drawn once at the largest length; each shorter case
+    takes their first T steps."""
+    prec = args.precision
+    dt = kfscan.dtype_for(prec)
+    Ts = [100, 1000, 10000, 100000, 1000000, 1 << 20]
+    Tmax = max(Ts)
+    n, m = 4, 2
+    rng = np.random.default_rng(args.seed)
+    model = W.paper_tv_model(Tmax, rng, n, m)
+    y = W.simulate(model, Tmax, rng)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt).contiguous()  # noqa: E731
+    full = [dv(a) for a in (model.F, model.Q, model.H, model.R, model.u, model.d)]
+    m0, P0, yd = dv(model.m0), dv(model.P0), dv(y)
+
+    def timed(T, scan, reps):
+        args_T = [a[:T] for a in full]
+        ms = []
+        outs = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            outs = kfscan.tv("filter", *args_T, m0, P0, yd[:T], precision=prec, scan=scan)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), outs
+
+    curve = []
+    for T in Ts:
+        timed(min(T, 1000), "sequential", 1)               # warm-up
+        t_seq, seq_out = timed(T, "sequential", 1)
+        timed(T, "lookback", max(1, args.warmup))
+        t_par, par_out = timed(T, "lookback", max(3, min(args.steps, 50)))
+        diff = float((seq_out[0] - par_out[0]).abs().max() / seq_out[0].abs().max())
+        curve.append({"T": T, "sequential_ms": t_seq, "parallel_ms": t_par,
+                      "speedup": t_seq / t_par, "m_filt_rel_diff": diff})
+        print("[speedup] T=%d sequential %.3f ms parallel %.4f ms speedup %.1f" %
+              (T, t_seq, t_par, t_seq / t_par), file=sys.stderr, flush=True)
+    top = curve[-1]
+    out = {
+        "metric": "speedup of the parallel Kalman filter over the sequential filter on one GPU lane",
+        "value": top["speedup"], "unit": "x", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": top["parallel_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "paper_tv_nx4_ny2_speedup", "T": Ts, "inputs": "u, d",
+                   "pipeline": "kf_filter_tv, scan lookback vs sequential", "seed": args.seed},
+        "paper": "up to about 750 (Apple M3 Max) and 500 (A100), FP32, in-place Ladner-Fischer",
+        "curve": curve,
     }
     print(json.dumps(out))
     return 0

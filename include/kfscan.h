@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define KFSCAN_ABI_VERSION 2
+#define KFSCAN_ABI_VERSION 3
 
 typedef enum kf_status {
     KF_OK = 0,
@@ -87,8 +87,16 @@ typedef enum kf_scan {
                                      time-invariant fold (see below)                 */
     KF_SCAN_BLELLOCH = 2,         /* Algorithm 2, one kernel per tree level          */
     KF_SCAN_HILLIS_STEELE = 3,    /* Algorithm 1, one kernel per doubling level      */
-    KF_SCAN_LOOKBACK_GENERIC = 4  /* the look-back scan folding full elements step by
+    KF_SCAN_LOOKBACK_GENERIC = 4, /* the look-back scan folding full elements step by
                                      step, with no use of time invariance            */
+    KF_SCAN_SEQUENTIAL = 5        /* no scan: the sequential recursions of Sec. III
+                                     (Kalman filter; RTS, or backward information
+                                     filter + two-filter combination), one GPU lane
+                                     per sequence -- the baseline of the speedup
+                                     experiment of Sec. VI.  Plain, batch and
+                                     time-varying entry points; its workspace is 256
+                                     bytes.  A ragged batch skips only the entries
+                                     that are themselves invalid (status bit 1)     */
 } kf_scan;
 
 typedef struct kf_problem {
@@ -114,7 +122,7 @@ typedef struct kf_batch {
     int32_t nx;            /* state dimension n                                   */
     int32_t ny;            /* measurement dimension m                             */
     int32_t precision;     /* kf_precision                                        */
-    int32_t scan;          /* KF_SCAN_AUTO, KF_SCAN_LOOKBACK or _LOOKBACK_GENERIC */
+    int32_t scan;          /* _AUTO, _LOOKBACK, _LOOKBACK_GENERIC or _SEQUENTIAL  */
     int64_t nseq;          /* number of sequences, 1 .. 2^22                      */
     int64_t nmodels;       /* 1 (shared model) or nseq (model i for sequence i)   */
     int64_t total_steps;   /* rows of y and of the outputs, >= sum of T[i]        */
@@ -137,7 +145,7 @@ typedef struct kf_batch {
  * prts_init1..2 with u, d) and scanned with the look-back scans over full
  * elements; the one-kernel-per-level scans are not offered (KF_ERR_UNSUPPORTED). */
 typedef struct kf_tv_problem {
-    int32_t nx, ny, precision, scan;       /* scan: KF_SCAN_AUTO, _LOOKBACK, _LOOKBACK_GENERIC */
+    int32_t nx, ny, precision, scan;       /* scan: _AUTO, _LOOKBACK, _LOOKBACK_GENERIC, _SEQUENTIAL */
     int64_t T;                             /* steps per sequence, >= 1          */
     int64_t nseq;                          /* sequences sharing the model, >= 1 */
     const void *F, *Q, *H, *R, *u, *d;     /* per-step model, device            */

@@ -35,7 +35,7 @@ bool shape_built(int nx, int ny) {
 static kf_status check_common(int nx, int ny, int precision, int scan) {
   if (nx < 1 || ny < 1) return KF_ERR_INVALID_ARG;
   if (precision < KF_PREC_F64 || precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
-  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_LOOKBACK_GENERIC) return KF_ERR_INVALID_ARG;
+  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_SEQUENTIAL) return KF_ERR_INVALID_ARG;
   if (!shape_built(nx, ny)) return KF_ERR_UNSUPPORTED;
   return KF_OK;
 }

@@ -2,6 +2,7 @@
 // per-precision translation units, which list the shapes that are built.
 #pragma once
 #include "kf_kernels.hpp"
+#include "kf_seq.hpp"
 #include "kf_tree.hpp"
 #include "kf_plan.hpp"
 
@@ -24,10 +25,69 @@ template <int LMAX, class Fn> void with_items(int L, Fn&& fn) {
   fn(std::integral_constant<int, 2>{});
 }
 
+// KF_SCAN_SEQUENTIAL: one lane per sequence, 64-lane blocks.  The prepare
+// stage only clears the error words.
+template <int N, int M, class P>
+kf_status run_sequential(Op op, int stages, const Job& p, char* ws, const Layout& L,
+                         hipStream_t st) {
+  using R = typename P::R;
+  constexpr int B = 64;
+  if (stages & ST_PREPARE)
+    hipLaunchKernelGGL((k_clear<256>), dim3(1), dim3(256), 0, st, reinterpret_cast<unsigned*>(ws),
+                       L.ctrl_words);
+  SeqArgs<R> a{};
+  a.F = static_cast<const R*>(p.F);
+  a.Q = static_cast<const R*>(p.Q);
+  a.H = static_cast<const R*>(p.H);
+  a.Rm = static_cast<const R*>(p.R);
+  a.u = p.tv ? static_cast<const R*>(p.u) : nullptr;
+  a.d = p.tv ? static_cast<const R*>(p.d) : nullptr;
+  a.m0 = static_cast<const R*>(p.m0);
+  a.P0 = static_cast<const R*>(p.P0);
+  a.T = p.T;
+  a.nseq = p.nseq;
+  if (p.batch) {
+    a.len = p.len;
+    a.row = p.row;
+    a.total_steps = p.total_steps;
+    a.model_stride = p.nmodels > 1 ? 1 : 0;
+  }
+  const dim3 grid((unsigned)((p.nseq + B - 1) / B));
+  const R* y = static_cast<const R*>(p.y);
+  R* mf = static_cast<R*>(p.m_filt);
+  R* Pf = static_cast<R*>(p.P_filt);
+  R* ms = static_cast<R*>(p.m_smooth);
+  R* Ps = static_cast<R*>(p.P_smooth);
+  if (stages & ST_FORWARD) {
+    a.err = reinterpret_cast<unsigned*>(ws + L.ctr[0]) + 2;
+    if (p.tv)
+      hipLaunchKernelGGL((k_seq_filter<N, M, P, true>), grid, dim3(B), 0, st, a, y, mf, Pf);
+    else
+      hipLaunchKernelGGL((k_seq_filter<N, M, P, false>), grid, dim3(B), 0, st, a, y, mf, Pf);
+  }
+  if (op != OP_FILTER && (stages & ST_BACKWARD)) {
+    a.err = reinterpret_cast<unsigned*>(ws + L.ctr[1]) + 2;
+    if (op == OP_RTS && p.tv)
+      hipLaunchKernelGGL((k_seq_rts<N, M, P, true>), grid, dim3(B), 0, st, a, (const R*)mf,
+                         (const R*)Pf, ms, Ps);
+    else if (op == OP_RTS)
+      hipLaunchKernelGGL((k_seq_rts<N, M, P, false>), grid, dim3(B), 0, st, a, (const R*)mf,
+                         (const R*)Pf, ms, Ps);
+    else if (p.tv)
+      hipLaunchKernelGGL((k_seq_twofilter<N, M, P, true>), grid, dim3(B), 0, st, a, y,
+                         (const R*)mf, (const R*)Pf, ms, Ps);
+    else
+      hipLaunchKernelGGL((k_seq_twofilter<N, M, P, false>), grid, dim3(B), 0, st, a, y,
+                         (const R*)mf, (const R*)Pf, ms, Ps);
+  }
+  return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+}
+
 template <int N, int M, class P>
 kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
                     hipStream_t st) {
   using R = typename P::R;
+  if (p.scan == KF_SCAN_SEQUENTIAL) return run_sequential<N, M, P>(op, stages, p, ws, L, st);
   constexpr int B = kBlock;
   constexpr int IT = items_per_thread(N);
   constexpr int ITI = items_ti(N);

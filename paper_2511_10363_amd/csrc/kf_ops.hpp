@@ -339,9 +339,9 @@ KF_DEV SElem<N, typename P::R> smooth_element(const typename P::R (&x)[N],
 // Two-filter combination (eqs. mean_tf_combination, cov_tf_combination):
 // x_s = (I + P J)^{-1}(x + P eta), P_s = (I + P J)^{-1} P, symmetrised by
 // averaging with its transpose.
-template <int N, class P>
+template <int N, class P, class TE>
 KF_DEV void tf_combine(const typename P::R (&x)[N], const typename P::R (&Pm)[N][N],
-                       const typename P::R (&eta)[N], const typename P::R (&J)[N][N],
+                       const TE (&eta)[N], const TE (&J)[N][N],
                        typename P::R (&xs)[N], typename P::R (&Ps)[N][N]) {
   using R = typename P::R;
   using S = typename P::S;

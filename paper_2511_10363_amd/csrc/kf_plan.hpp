@@ -102,7 +102,7 @@ inline Job job_of(const kf_tv_problem& p) {
   j.ny = p.ny;
   j.precision = p.precision;
   // the per-step elements are folded by the look-back scans over full elements
-  j.scan = KF_SCAN_LOOKBACK_GENERIC;
+  j.scan = p.scan == KF_SCAN_SEQUENTIAL ? KF_SCAN_SEQUENTIAL : KF_SCAN_LOOKBACK_GENERIC;
   j.T = p.T;
   j.nseq = p.nseq;
   j.batch = false;
@@ -153,6 +153,16 @@ inline Layout make_layout(const Job& j) {
   const long n = j.nx, m = j.ny, T = j.T, nseq = j.nseq;
   const int scan = j.scan;
   Layout L{};
+  if (scan == KF_SCAN_SEQUENTIAL) {
+    // the sequential recursions need only the error words of the two slots
+    L.ctr[0] = 0;
+    L.ctr[1] = 4 * sizeof(unsigned);
+    L.ctrl_words = 8;
+    L.cst = L.tree[0] = L.tree[1] = 256;
+    L.tile_start[0] = L.tile_start[1] = L.tile_map[0] = L.tile_map[1] = 256;
+    L.total = 256;
+    return L;
+  }
   // A ragged batch always takes the longest tiles, so that each sequence is
   // tiled, scanned and rounded the same whatever else is in the batch.
   const int lf = (scan == KF_SCAN_LOOKBACK_GENERIC) ? items_per_thread(j.nx) : items_ti(j.nx);

@@ -26,7 +26,8 @@ LIB_PATH = os.path.join(_HERE, "libkfscan.so")
 
 KF_OK, KF_ERR_INVALID_ARG, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE, KF_ERR_DEVICE = range(5)
 PRECISIONS = {"f64": 0, "f32": 1, "mixed": 2}
-SCANS = {"auto": 0, "lookback": 1, "blelloch": 2, "hillis_steele": 3, "lookback_generic": 4}
+SCANS = {"auto": 0, "lookback": 1, "blelloch": 2, "hillis_steele": 3, "lookback_generic": 4,
+         "sequential": 5}
 _VOIDP = ctypes.c_void_p
 
 

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(kfscan):
 
 def test_abi_version_and_status_strings(kfscan):
     lib = kfscan.load_library()
-    assert lib.kf_abi_version() == 2
+    assert lib.kf_abi_version() == 3
     for code in range(5):
         assert kfscan.status_string(code)
 
@@ -143,3 +143,24 @@ def test_tv_workspace_size_and_validation(kfscan):
     p = tvp(T=100)
     for name in ("kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv"):
         assert getattr(lib, name)(ctypes.byref(p), None, 0, None) == 1   # null pointers
+
+
+def test_sequential_workspace_is_one_line_of_control_words(kfscan):
+    """KF_SCAN_SEQUENTIAL needs only the error words, for every entry kind,
+    whatever the length; scan values past it are refused."""
+    lib = kfscan.load_library()
+    n = ctypes.c_size_t(0)
+    seq = kfscan.SCANS["sequential"]
+    assert seq == 5
+    for T, nseq in ((1, 1), (1 << 30, 1), (1000, 1 << 20)):
+        assert lib.kf_workspace_size(ctypes.byref(_problem(kfscan, T=T, nseq=nseq, scan=seq)),
+                                     ctypes.byref(n)) == 0
+        assert n.value == 256
+    assert lib.kf_batch_workspace_size(ctypes.byref(_batch(kfscan, scan=seq, nmodels=100)),
+                                       ctypes.byref(n)) == 0
+    assert n.value == 256
+    p = kfscan.KfTvProblem()
+    p.nx, p.ny, p.precision, p.scan, p.T, p.nseq = 4, 2, 1, seq, 1 << 20, 1
+    assert lib.kf_tv_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    assert n.value == 256
+    assert lib.kf_workspace_size(ctypes.byref(_problem(kfscan, scan=6)), ctypes.byref(n)) == 1

@@ -24,11 +24,16 @@ def _cast(a, prec):
     return a if prec == "f64" else np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-def _check_tv(entry, T, prec, inputs, seed, nx=4, ny=2, nseq=1):
-    _say("tv", entry, prec, "T=%d" % T, "inputs" if inputs else "no inputs", "nseq=%d" % nseq)
+def _check_tv(entry, T, prec, inputs, seed, nx=4, ny=2, nseq=1, scan="auto", ridge=0.0):
+    _say("tv", entry, prec, scan, "T=%d" % T, "inputs" if inputs else "no inputs",
+         "nseq=%d" % nseq)
     k = kfscan()
     rng = np.random.default_rng(seed)
     model = W.paper_tv_model(T, rng, nx, ny)
+    if ridge:
+        # better-conditioned noise covariances: Q_k + ridge I, R_k + ridge I
+        model.Q = model.Q + ridge * np.eye(nx)
+        model.R = model.R + ridge * np.eye(ny)
     if not inputs:
         model.u = np.zeros((T, nx))
         model.d = np.zeros((T, ny))
@@ -38,7 +43,7 @@ def _check_tv(entry, T, prec, inputs, seed, nx=4, ny=2, nseq=1):
     u = dev(model.u) if inputs else None
     d = dev(model.d) if inputs else None
     got = k.tv(entry, dev(model.F), dev(model.Q), dev(model.H), dev(model.R), u, d,
-               dev(model.m0), dev(model.P0), dev(ys), precision=prec)
+               dev(model.m0), dev(model.P0), dev(ys), precision=prec, scan=scan)
     torch.cuda.synchronize()
     got = [g.double().cpu().numpy() for g in got]
     arrs = [_cast(a, prec) for a in (model.F, model.Q, model.H, model.R, model.m0, model.P0)]
