@@ -79,17 +79,19 @@ def main() -> int:
     ap.add_argument("--smoother", default="rts", choices=["rts", "tf"],
                     help="RTS (Algorithm 6) or two-filter (Algorithm 7) backward pass")
     ap.add_argument("--scan", default="lookback",
-                    choices=["lookback", "lookback_generic", "blelloch", "hillis_steele"])
+                    choices=["lookback", "lookback_generic", "blelloch", "hillis_steele",
+                             "ladner_fischer", "sengupta_a", "sengupta_b", "sequential"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
     ap.add_argument("--workload", default="tracking",
-                    choices=["tracking", "batched", "serving", "tv", "speedup"],
+                    choices=["tracking", "batched", "serving", "tv", "speedup", "scans"],
                     help="tracking: one long sequence (the headline); batched: 4096 ragged "
                          "sequences, a random stable model each; serving: Poisson job "
                          "arrivals served in ragged batches; tv: the paper's time-varying "
                          "model with inputs; speedup: the parallel filter against the "
-                         "sequential filter on one GPU lane, over a range of T")
+                         "sequential filter on one GPU lane, over a range of T; scans: "
+                         "every scan algorithm with each of the three pipelines")
     ap.add_argument("--jobs", type=int, default=2000, help="jobs of the serving workload")
     ap.add_argument("--nseq", type=int, default=4096, help="sequences of the batched workload")
     args = ap.parse_args()
@@ -116,6 +118,8 @@ def main() -> int:
         return bench_tv(args, np, torch, W, kfscan, dev)
     if args.workload == "speedup":
         return bench_speedup(args, np, torch, W, kfscan, dev)
+    if args.workload == "scans":
+        return bench_scans(args, np, torch, W, kfscan, dev)
     T = args.T if args.T > 0 else 1 << args.log2T
     tname = ("T2^%d" % args.log2T) if args.T <= 0 else ("T%d" % T)
     prec = args.precision
@@ -637,11 +641,15 @@ def bench_speedup(args, np, torch, W, kfscan, dev) -> int:
         t_seq, seq_out = timed(T, "sequential", 1)
         timed(T, "lookback", max(1, args.warmup))
         t_par, par_out = timed(T, "lookback", max(3, min(args.steps, 50)))
+        timed(T, "ladner_fischer", 1)
+        t_lf, _ = timed(T, "ladner_fischer", max(3, min(args.steps, 20)))
         diff = float((seq_out[0] - par_out[0]).abs().max() / seq_out[0].abs().max())
         curve.append({"T": T, "sequential_ms": t_seq, "parallel_ms": t_par,
-                      "speedup": t_seq / t_par, "m_filt_rel_diff": diff})
-        print("[speedup] T=%d sequential %.3f ms parallel %.4f ms speedup %.1f" %
-              (T, t_seq, t_par, t_seq / t_par), file=sys.stderr, flush=True)
+                      "speedup": t_seq / t_par, "ladner_fischer_ms": t_lf,
+                      "speedup_ladner_fischer": t_seq / t_lf, "m_filt_rel_diff": diff})
+        print("[speedup] T=%d sequential %.3f ms look-back %.4f ms (x%.1f) "
+              "Ladner-Fischer %.4f ms (x%.1f)" % (T, t_seq, t_par, t_seq / t_par, t_lf,
+                                                   t_seq / t_lf), file=sys.stderr, flush=True)
     top = curve[-1]
     out = {
         "metric": "speedup of the parallel Kalman filter over the sequential filter on one GPU lane",
@@ -651,9 +659,74 @@ def bench_speedup(args, np, torch, W, kfscan, dev) -> int:
         "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
         "data": "synthetic",
         "config": {"workload": "paper_tv_nx4_ny2_speedup", "T": Ts, "inputs": "u, d",
-                   "pipeline": "kf_filter_tv, scan lookback vs sequential", "seed": args.seed},
+                   "pipeline": "kf_filter_tv: look-back scan (value) and in-place "
+                               "Ladner-Fischer against the sequential filter",
+                   "seed": args.seed},
         "paper": "up to about 750 (Apple M3 Max) and 500 (A100), FP32, in-place Ladner-Fischer",
         "curve": curve,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def bench_scans(args, np, torch, W, kfscan, dev) -> int:
+    """The paper's comparison of scan algorithms (Sec. VI-B..D): PKF, PRTS and
+    PTFS with every scan -- the look-back scan over full elements, the
+    one-kernel-per-level Hillis-Steele, Blelloch, in-place Ladner-Fischer,
+    Sengupta A and B -- and the sequential recursions, on the paper's
+    time-varying model (nx = 4, ny = 2, inputs), FP32, T = 10^3 .. 10^6.
+    Each cell is the median of event-timed one-call runs (kf_*_tv).  The model
+    and data are drawn once at 10^6 steps; shorter cases take their first T."""
+    prec = args.precision
+    dt = kfscan.dtype_for(prec)
+    Ts = [1000, 10000, 100000, 1000000]
+    scans = ["lookback", "hillis_steele", "blelloch", "ladner_fischer", "sengupta_a",
+             "sengupta_b", "sequential"]
+    n, m = 4, 2
+    rng = np.random.default_rng(args.seed)
+    model = W.paper_tv_model(max(Ts), rng, n, m)
+    y = W.simulate(model, max(Ts), rng)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt).contiguous()  # noqa: E731
+    full = [dv(a) for a in (model.F, model.Q, model.H, model.R, model.u, model.d)]
+    m0, P0, yd = dv(model.m0), dv(model.P0), dv(y)
+    ws = torch.empty(1, dtype=torch.uint8, device=dev)
+    table = []
+    for T in Ts:
+        arrs = [a[:T] for a in full]
+        for scan in scans:
+            row = {"T": T, "scan": scan}
+            for entry in ("filter", "rts", "tf"):
+                reps = 1 if scan == "sequential" else max(3, min(args.steps, 10))
+                kfscan.tv(entry, *arrs, m0, P0, yd[:T], precision=prec, scan=scan)
+                ms = []
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    kfscan.tv(entry, *arrs, m0, P0, yd[:T], precision=prec, scan=scan)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+                row[{"filter": "PKF_ms", "rts": "PRTS_ms", "tf": "PTFS_ms"}[entry]] = \
+                    float(np.median(ms))
+            if scan not in ("lookback", "sequential"):
+                row["combines"], row["steps"] = kfscan.scan_counts(scan, T)
+            table.append(row)
+            print("[scans] T=%d %-15s PKF %.3f  PRTS %.3f  PTFS %.3f ms" %
+                  (T, scan, row["PKF_ms"], row["PRTS_ms"], row["PTFS_ms"]), file=sys.stderr,
+                  flush=True)
+    del ws
+    best = min((r for r in table if r["T"] == max(Ts)), key=lambda r: r["PKF_ms"])
+    out = {
+        "metric": "time of one PKF / PRTS / PTFS call per scan algorithm (the paper's model)",
+        "value": best["PKF_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": best["PKF_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "mixed": "f32+f64solve", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "paper_tv_nx4_ny2_scan_comparison", "T": Ts, "scans": scans,
+                   "fastest_PKF_at_1e6": best["scan"], "seed": args.seed},
+        "table": table,
     }
     print(json.dumps(out))
     return 0

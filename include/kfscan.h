@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define KFSCAN_ABI_VERSION 3
+#define KFSCAN_ABI_VERSION 4
 
 typedef enum kf_status {
     KF_OK = 0,
@@ -89,7 +89,7 @@ typedef enum kf_scan {
     KF_SCAN_HILLIS_STEELE = 3,    /* Algorithm 1, one kernel per doubling level      */
     KF_SCAN_LOOKBACK_GENERIC = 4, /* the look-back scan folding full elements step by
                                      step, with no use of time invariance            */
-    KF_SCAN_SEQUENTIAL = 5        /* no scan: the sequential recursions of Sec. III
+    KF_SCAN_SEQUENTIAL = 5,       /* no scan: the sequential recursions of Sec. III
                                      (Kalman filter; RTS, or backward information
                                      filter + two-filter combination), one GPU lane
                                      per sequence -- the baseline of the speedup
@@ -97,7 +97,15 @@ typedef enum kf_scan {
                                      time-varying entry points; its workspace is 256
                                      bytes.  A ragged batch skips only the entries
                                      that are themselves invalid (status bit 1)     */
+    KF_SCAN_LADNER_FISCHER = 6,   /* Algorithm 3 (in place), one kernel per level    */
+    KF_SCAN_SENGUPTA_A = 7,       /* Algorithm 4 with N = 1, one kernel per level    */
+    KF_SCAN_SENGUPTA_B = 8        /* Algorithm 4 with N = 16384 (Hillis-Steele on the
+                                     top 16384 positions), one kernel per level     */
 } kf_scan;
+/* The one-kernel-per-level scans (_BLELLOCH, _HILLIS_STEELE, _LADNER_FISCHER,
+ * _SENGUPTA_A, _SENGUPTA_B) keep every element in the workspace (Hillis-
+ * Steele and Sengupta need two such arrays) and are offered for kf_problem and
+ * kf_tv_problem with nseq <= 65535, not for ragged batches. */
 
 typedef struct kf_problem {
     int32_t nx;            /* state dimension n   (see kf_supported)              */
@@ -145,7 +153,7 @@ typedef struct kf_batch {
  * prts_init1..2 with u, d) and scanned with the look-back scans over full
  * elements; the one-kernel-per-level scans are not offered (KF_ERR_UNSUPPORTED). */
 typedef struct kf_tv_problem {
-    int32_t nx, ny, precision, scan;       /* scan: _AUTO, _LOOKBACK, _LOOKBACK_GENERIC, _SEQUENTIAL */
+    int32_t nx, ny, precision, scan;       /* any kf_scan                       */
     int64_t T;                             /* steps per sequence, >= 1          */
     int64_t nseq;                          /* sequences sharing the model, >= 1 */
     const void *F, *Q, *H, *R, *u, *d;     /* per-step model, device            */
@@ -221,6 +229,15 @@ kf_status kf_smooth_rts_batch(const kf_batch *b, void *workspace, size_t workspa
                               void *stream);
 kf_status kf_smooth_twofilter_batch(const kf_batch *b, void *workspace, size_t workspace_bytes,
                                     void *stream);
+
+/* Instrumentation of the one-kernel-per-level scans: the number of
+ * applications of the associative operator (*combines) and of dependent
+ * parallel steps that apply it (*steps) in one scan over T elements of one
+ * sequence, counted from the same launch plan the scan enqueues (padding
+ * positions included).  The work and span of Algorithms 1-4 (Sec. II).
+ * KF_ERR_UNSUPPORTED for the other scans, whose work depends on the data
+ * (look-back) or which do not scan (sequential). */
+kf_status kf_scan_counts(int32_t scan, int64_t T, int64_t *combines, int64_t *steps);
 
 /* ---- Time-varying models ----------------------------------------------- */
 kf_status kf_tv_workspace_size(const kf_tv_problem *p, size_t *bytes);

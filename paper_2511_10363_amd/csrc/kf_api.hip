@@ -35,7 +35,7 @@ bool shape_built(int nx, int ny) {
 static kf_status check_common(int nx, int ny, int precision, int scan) {
   if (nx < 1 || ny < 1) return KF_ERR_INVALID_ARG;
   if (precision < KF_PREC_F64 || precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
-  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_SEQUENTIAL) return KF_ERR_INVALID_ARG;
+  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_SENGUPTA_B) return KF_ERR_INVALID_ARG;
   if (!shape_built(nx, ny)) return KF_ERR_UNSUPPORTED;
   return KF_OK;
 }
@@ -75,7 +75,7 @@ static kf_status check_tv(const kf_tv_problem* p) {
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
   if (s != KF_OK) return s;
-  if (is_tree_scan(p->scan)) return KF_ERR_UNSUPPORTED;
+  if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
   return check_layout(job_of(*p));
 }
 
@@ -177,6 +177,21 @@ kf_status kf_tv_workspace_size(const kf_tv_problem* p, size_t* bytes) {
   kf_status s = kfs::check_tv(p);
   if (s != KF_OK) return s;
   *bytes = kfs::make_layout(kfs::job_of(*p)).total;
+  return KF_OK;
+}
+
+kf_status kf_scan_counts(int32_t scan, int64_t T, int64_t* combines, int64_t* steps) {
+  if (!combines || !steps || T < 1 || T > (int64_t(1) << 40)) return KF_ERR_INVALID_ARG;
+  if (scan < KF_SCAN_AUTO || scan > KF_SCAN_SENGUPTA_B) return KF_ERR_INVALID_ARG;
+  if (!kfs::is_tree_scan(scan)) return KF_ERR_UNSUPPORTED;
+  int64_t c = 0, n = 0;
+  for (const kfs::TreeStep& t : kfs::tree_plan(scan, T))
+    if (t.threads > 0 && t.combines > 0) {
+      c += t.combines;
+      ++n;
+    }
+  *combines = c;
+  *steps = n;
   return KF_OK;
 }
 

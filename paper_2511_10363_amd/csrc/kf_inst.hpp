@@ -10,6 +10,10 @@
 
 namespace kfs {
 
+template <class T> struct TypeTag {
+  using type = T;
+};
+
 // Calls fn(std::integral_constant<int, L>{}) for the runtime L in {2, 4, 8,
 // 16}, instantiating only the values up to LMAX.
 template <int LMAX, class Fn> void with_items(int L, Fn&& fn) {
@@ -136,16 +140,26 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
   R* ms = static_cast<R*>(p.m_smooth);
   R* Ps = static_cast<R*>(p.P_smooth);
   if (is_tree_scan(p.scan)) {
-    const bool hs = (p.scan == KF_SCAN_HILLIS_STEELE);
     R* X0 = reinterpret_cast<R*>(ws + L.tree[0]);
     R* X1 = reinterpret_cast<R*>(ws + L.tree[1]);
-    TreeIO<R> io{cst, y, mf, Pf, mf, Pf, p.T, L.tree_positions};
-    if (stages & ST_FORWARD) tree_scan<TreeFilter<N, M, P>>(io, hs, p.nseq, X0, X1, st);
+    TreeIO<R> io{cst, y, mf, Pf, mf, Pf, p.T, L.tree_positions, tvm};
+    auto scan = [&](auto tag) {
+      tree_scan<typename decltype(tag)::type>(io, p.scan, p.nseq, X0, X1, st);
+    };
+    if (stages & ST_FORWARD) {
+      if (p.tv) scan(TypeTag<TreeFilter<N, M, P, true>>{});
+      else scan(TypeTag<TreeFilter<N, M, P>>{});
+    }
     if (op != OP_FILTER && (stages & ST_BACKWARD)) {
       io.m_out = ms;
       io.P_out = Ps;
-      if (op == OP_RTS) tree_scan<TreeRts<N, M, P>>(io, hs, p.nseq, X0, X1, st);
-      else tree_scan<TreeTwoFilter<N, M, P>>(io, hs, p.nseq, X0, X1, st);
+      if (op == OP_RTS) {
+        if (p.tv) scan(TypeTag<TreeRts<N, M, P, true>>{});
+        else scan(TypeTag<TreeRts<N, M, P>>{});
+      } else {
+        if (p.tv) scan(TypeTag<TreeTwoFilter<N, M, P, true>>{});
+        else scan(TypeTag<TreeTwoFilter<N, M, P>>{});
+      }
     }
     return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
   }

@@ -52,7 +52,7 @@ struct Layout {
   size_t pre[2];              // published anchored prefixes (tagged 64-bit words)
   size_t ctrl_words;          // 32-bit words of the control region at offset 0
   size_t cst;                 // derived model quantities
-  size_t tree[2];             // element buffers of the tree scans (Hillis-Steele: both)
+  size_t tree[2];             // element buffers of the tree scans (HS, Sengupta: both)
   long tree_positions;        // scan positions per sequence of the tree scans
   int items[2];               // steps per thread of the forward and backward scans
   long ntiles[2];             // tiles per sequence (equal-length sequences)
@@ -79,6 +79,13 @@ struct Job {
   const void *u, *d;          // time-varying model: may be null
 };
 
+// The scans with one kernel launch per tree level (kf_tree.hpp).
+inline bool is_tree_scan(int scan) {
+  return scan == KF_SCAN_BLELLOCH || scan == KF_SCAN_HILLIS_STEELE ||
+         scan == KF_SCAN_LADNER_FISCHER || scan == KF_SCAN_SENGUPTA_A ||
+         scan == KF_SCAN_SENGUPTA_B;
+}
+
 inline Job job_of(const kf_problem& p) {
   Job j{};
   j.nx = p.nx;
@@ -102,7 +109,8 @@ inline Job job_of(const kf_tv_problem& p) {
   j.ny = p.ny;
   j.precision = p.precision;
   // the per-step elements are folded by the look-back scans over full elements
-  j.scan = p.scan == KF_SCAN_SEQUENTIAL ? KF_SCAN_SEQUENTIAL : KF_SCAN_LOOKBACK_GENERIC;
+  j.scan = (p.scan == KF_SCAN_SEQUENTIAL || is_tree_scan(p.scan)) ? p.scan
+                                                                  : KF_SCAN_LOOKBACK_GENERIC;
   j.T = p.T;
   j.nseq = p.nseq;
   j.batch = false;
@@ -134,10 +142,6 @@ inline Job job_of(const kf_batch& b) {
   j.y = b.y;
   j.m_filt = b.m_filt; j.P_filt = b.P_filt; j.m_smooth = b.m_smooth; j.P_smooth = b.P_smooth;
   return j;
-}
-
-inline bool is_tree_scan(int scan) {
-  return scan == KF_SCAN_BLELLOCH || scan == KF_SCAN_HILLIS_STEELE;
 }
 
 inline long tree_positions_for(int scan, long T) {
@@ -218,7 +222,9 @@ inline Layout make_layout(const Job& j) {
     L.tree[0] = off;
     off = align256(off + buf);
     L.tree[1] = off;
-    if (scan == KF_SCAN_HILLIS_STEELE) off = align256(off + buf);
+    if (scan == KF_SCAN_HILLIS_STEELE || scan == KF_SCAN_SENGUPTA_A ||
+        scan == KF_SCAN_SENGUPTA_B)
+      off = align256(off + buf);
   }
   L.total = off;
   return L;

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libkfscan.so")
 KF_OK, KF_ERR_INVALID_ARG, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE, KF_ERR_DEVICE = range(5)
 PRECISIONS = {"f64": 0, "f32": 1, "mixed": 2}
 SCANS = {"auto": 0, "lookback": 1, "blelloch": 2, "hillis_steele": 3, "lookback_generic": 4,
-         "sequential": 5}
+         "sequential": 5, "ladner_fischer": 6, "sengupta_a": 7, "sengupta_b": 8}
 _VOIDP = ctypes.c_void_p
 
 
@@ -73,7 +73,8 @@ EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_s
            "kf_smooth_twofilter", "kf_prepare", "kf_pass_filter", "kf_pass_rts",
            "kf_pass_twofilter", "kf_batch_workspace_size", "kf_filter_batch",
            "kf_smooth_rts_batch", "kf_smooth_twofilter_batch", "kf_workspace_status",
-           "kf_tv_workspace_size", "kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv")
+           "kf_tv_workspace_size", "kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv",
+           "kf_scan_counts")
 STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
 # When set (the tests set it), every call synchronises and checks the
 # workspace's look-back timeout flag.
@@ -114,6 +115,9 @@ def load_library(path: str = LIB_PATH):
         lib.kf_workspace_status.restype = ctypes.c_int
         lib.kf_workspace_status.argtypes = [_VOIDP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32),
                                             _VOIDP]
+        lib.kf_scan_counts.restype = ctypes.c_int
+        lib.kf_scan_counts.argtypes = [ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         lib.kf_device_copy.restype = ctypes.c_int
         lib.kf_device_copy.argtypes = [_VOIDP, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_workspace_timed_out.restype = ctypes.c_int
@@ -463,6 +467,15 @@ def device_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
     stream = torch.cuda.current_stream(src.device).cuda_stream
     _check(load_library().kf_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream),
            "kf_device_copy")
+
+
+def scan_counts(scan: str, T: int) -> tuple[int, int]:
+    """(operator applications, parallel steps that apply it) of one scan of
+    kind ``scan`` over T elements (kf_scan_counts)."""
+    c, n = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().kf_scan_counts(SCANS[scan], T, ctypes.byref(c), ctypes.byref(n)),
+           "kf_scan_counts")
+    return c.value, n.value
 
 
 def supported(nx: int, ny: int, precision: str = "f32") -> bool:

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(kfscan):
 
 def test_abi_version_and_status_strings(kfscan):
     lib = kfscan.load_library()
-    assert lib.kf_abi_version() == 3
+    assert lib.kf_abi_version() == 4
     for code in range(5):
         assert kfscan.status_string(code)
 
@@ -139,7 +139,8 @@ def test_tv_workspace_size_and_validation(kfscan):
     assert size(tvp()) == 0 and n.value > 0
     assert size(tvp(T=0)) == 1
     assert size(tvp(nx=5)) == 2
-    assert size(tvp(scan=3)) == 2          # tree scans are not offered for time-varying models
+    assert size(tvp(scan=3)) == 0          # tree scans serve time-varying models too
+    assert size(tvp(scan=3, nseq=70000)) == 2
     p = tvp(T=100)
     for name in ("kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv"):
         assert getattr(lib, name)(ctypes.byref(p), None, 0, None) == 1   # null pointers
@@ -163,4 +164,80 @@ def test_sequential_workspace_is_one_line_of_control_words(kfscan):
     p.nx, p.ny, p.precision, p.scan, p.T, p.nseq = 4, 2, 1, seq, 1 << 20, 1
     assert lib.kf_tv_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
     assert n.value == 256
-    assert lib.kf_workspace_size(ctypes.byref(_problem(kfscan, scan=6)), ctypes.byref(n)) == 1
+    assert lib.kf_workspace_size(ctypes.byref(_problem(kfscan, scan=9)), ctypes.byref(n)) == 1
+
+
+def test_tree_scan_workspace_sizes(kfscan):
+    """Element arrays in the workspace: Blelloch and Ladner-Fischer one padded
+    array, Hillis-Steele two of T positions, Sengupta two padded ones."""
+    lib = kfscan.load_library()
+    n = ctypes.c_size_t(0)
+
+    def size(scan, T):
+        assert lib.kf_workspace_size(ctypes.byref(_problem(kfscan, T=T, scan=kfscan.SCANS[scan])),
+                                     ctypes.byref(n)) == 0
+        return n.value
+    T = 100000
+    base = size("lookback_generic", T)
+    one = (3 * 16 + 2 * 4) * 4                             # FP32 filtering element, nx = 4
+    assert size("ladner_fischer", T) - base >= one * (1 << 17)
+    assert size("blelloch", T) == size("ladner_fischer", T)
+    assert size("sengupta_a", T) - base >= 2 * one * (1 << 17)
+    assert size("sengupta_b", T) == size("sengupta_a", T)
+    assert size("hillis_steele", T) - base >= 2 * one * T
+
+
+def _oracle_counts(name, T, N=None):
+    """Operator applications of the oracle's scan over T elements (a cheap
+    associative operator; only the count matters here)."""
+    from oracle import scans
+    cnt = [0]
+
+    def op(x, y):
+        cnt[0] += 1
+        return x + y
+    if name == "sengupta":
+        scans.sengupta(list(range(T)), op, 0, N=N)
+    else:
+        scans.ALL[name](list(range(T)), op, 0)
+    return cnt[0]
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 8, 100, 1024, 5000, 1 << 15, 100000])
+def test_scan_counts_match_the_oracle_algorithms(kfscan, T):
+    """kf_scan_counts, read off the launch plan, equals the number of operator
+    applications of the oracle's Algorithms 1-4 on the same length.  The
+    GPU Blelloch rebuilds only the T real elements in its final pass, the
+    oracle all P padded ones."""
+    P = 1 << max(0, (T - 1).bit_length())
+    assert kfscan.scan_counts("hillis_steele", T)[0] == _oracle_counts("hillis_steele", T)
+    assert kfscan.scan_counts("ladner_fischer", T)[0] == _oracle_counts("ladner_fischer", T)
+    assert kfscan.scan_counts("sengupta_a", T)[0] == _oracle_counts("sengupta", T, 1)
+    assert kfscan.scan_counts("sengupta_b", T)[0] == _oracle_counts("sengupta", T, 16384)
+    assert kfscan.scan_counts("blelloch", T)[0] == _oracle_counts("blelloch", T) - (P - T)
+
+
+@pytest.mark.parametrize("T", [2, 16, 1024, 1 << 20])
+def test_scan_steps_and_work(kfscan, T):
+    """Span and work of Sec. II for T a power of two: Hillis-Steele log2 T
+    steps and T log2 T - T + 1 applications; Blelloch 2 log2 T + 1 steps
+    (with the final pass) and 3T - 2; in-place Ladner-Fischer two steps fewer,
+    2 log2 T - 1, and 2T - 2 - log2 T, which Sengupta A matches."""
+    lg = T.bit_length() - 1
+    assert kfscan.scan_counts("hillis_steele", T) == (T * lg - T + 1, lg)
+    assert kfscan.scan_counts("blelloch", T) == (3 * T - 2, 2 * lg + 1)
+    assert kfscan.scan_counts("ladner_fischer", T) == (2 * T - 2 - lg, 2 * lg - 1)
+    assert kfscan.scan_counts("sengupta_a", T) == (2 * T - 2 - lg, 2 * lg - 1)
+    N = min(T, 16384)
+    dstar = (T // N).bit_length() - 1
+    want = 2 * (T - N) - dstar + N * (N.bit_length() - 1) - N + 1
+    assert kfscan.scan_counts("sengupta_b", T)[0] == want
+
+
+def test_scan_counts_refuse_other_scans(kfscan):
+    lib = kfscan.load_library()
+    c, n = ctypes.c_int64(0), ctypes.c_int64(0)
+    for scan in ("auto", "lookback", "lookback_generic", "sequential"):
+        assert lib.kf_scan_counts(kfscan.SCANS[scan], 1000, ctypes.byref(c), ctypes.byref(n)) == 2
+    assert lib.kf_scan_counts(kfscan.SCANS["blelloch"], 0, ctypes.byref(c), ctypes.byref(n)) == 1
+    assert lib.kf_scan_counts(9, 10, ctypes.byref(c), ctypes.byref(n)) == 1

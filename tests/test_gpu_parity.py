@@ -61,7 +61,8 @@ def _check(entry, model, y, prec, tol=None, scan="auto"):
 
 
 SCAN_KINDS = ["lookback", "lookback_generic"]
-TREE_KINDS = ["blelloch", "hillis_steele"]    # one kernel per tree level (Algorithms 1, 2)
+TREE_KINDS = ["blelloch", "hillis_steele", "ladner_fischer", "sengupta_a",
+              "sengupta_b"]             # one kernel per tree level (Algorithms 1-4)
 ALL_KINDS = SCAN_KINDS + TREE_KINDS
 
 
@@ -159,6 +160,16 @@ def test_intermediate_tile_sizes(entry, prec):
     T = (1 << 19) + 12345
     model, y = W.tracking(T, seed=19)
     _check(entry, model, y, prec)
+
+
+@pytest.mark.parametrize("scan", TREE_KINDS)
+@pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
+def test_tree_scans_past_the_sengupta_threshold(entry, scan):
+    """T = 100000 pads to 2^17: Sengupta B reduces three levels down to its
+    16384-position top level before Hillis-Steele, and every other tree scan
+    runs many levels over a ragged tail of identity padding."""
+    model, y = W.tracking(100000, seed=17)
+    _check(entry, model, y, "f64", scan=scan)
 
 
 def test_full_size_twofilter_T_2_18():

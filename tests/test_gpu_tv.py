@@ -93,6 +93,22 @@ def test_time_varying_batch_of_sequences(entry):
     _check_tv(entry, 3000, "f64", True, seed=5, nseq=3)
 
 
+@pytest.mark.parametrize("scan", ["blelloch", "hillis_steele", "ladner_fischer", "sengupta_a",
+                                  "sengupta_b"])
+@pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
+def test_time_varying_tree_scans(entry, scan):
+    """The one-kernel-per-level scans over the per-step elements, at a length
+    past Sengupta B's threshold (T = 40000 pads to 2^16)."""
+    _check_tv(entry, 40000, "f64", True, seed=9, scan=scan)
+
+
+@pytest.mark.parametrize("entry", ["filter", "rts"])
+def test_time_varying_ladner_fischer_f32(entry):
+    """The configuration of the paper's speedup experiment: FP32, in-place
+    Ladner-Fischer, the time-varying model with inputs."""
+    _check_tv(entry, 20000, "f32", True, seed=10, scan="ladner_fischer")
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (3, 2), (4, 4)])
 def test_time_varying_shapes(nx, ny):
     _check_tv("rts", 2500, "f64", True, seed=nx * 7 + ny, nx=nx, ny=ny)
