@@ -6,10 +6,10 @@
 // scans for comparison (KF_SCAN_HILLIS_STEELE, _BLELLOCH, _LADNER_FISCHER,
 // _SENGUPTA_A, _SENGUPTA_B).
 //
-// Elements are stored as a structure of arrays per sequence: scalar f of scan
-// position p of sequence s in a level of n positions sits at
-// X[(s * SIZE + f) * n + p], so the threads of a level read and write
-// consecutive addresses.  Scan order is time order for the filter and
+// Sequence s of a level of n positions occupies SIZE * n scalars from
+// (s * SIZE * n).  Inside, the in-place scans (Blelloch, Ladner-Fischer) store
+// each element whole; Hillis-Steele and Sengupta, whose levels are read at
+// consecutive positions, store a structure of arrays (elem_load).  Scan order is time order for the filter and
 // descending time for the two reverse scans (position p is row T-1-p), whose
 // operator takes its operands swapped (reading of the reversed all-prefix-sums
 // of Sec. II-B), as in the look-back kernels.  Positions p >= T hold the
@@ -41,11 +41,32 @@ template <class R> struct TreeIO {
   TvModel<R> tv;   // per-step model of a time-varying problem (else unused)
 };
 
-template <class E, class R> KF_DEV void soa_load(E& x, const R* __restrict__ X, long n, long p) {
-  each(x, [&](R& v, int f) { v = X[(long)f * n + p]; });
+// Element p of a level of n positions, in one of two layouts.  AOS: the
+// element's SIZE scalars are contiguous, so a lane moves whole 16-byte pieces
+// of one element and every cache line it fetches is used whole, also when the
+// lanes of a wave touch elements 2s apart (the upper levels of the in-place
+// up- and down-sweeps).  Structure of arrays: scalar f of all positions is
+// contiguous, so a wave reading consecutive positions issues one line-sized
+// request per scalar -- fewer requests than AOS when the positions are
+// consecutive (Hillis-Steele levels, Sengupta's reduce and down-sweep), but
+// one line per scalar and lane once the stride passes a line.
+template <bool AOS, class E, class R>
+KF_DEV void elem_load(E& x, const R* __restrict__ X, long n, long p) {
+  if constexpr (AOS) {
+    const R* __restrict__ e = X + p * (long)E::SIZE;
+    each(x, [&](R& v, int f) { v = e[f]; });
+  } else {
+    each(x, [&](R& v, int f) { v = X[(long)f * n + p]; });
+  }
 }
-template <class E, class R> KF_DEV void soa_store(R* __restrict__ X, long n, long p, E& x) {
-  each(x, [&](R& v, int f) { X[(long)f * n + p] = v; });
+template <bool AOS, class E, class R>
+KF_DEV void elem_store(R* __restrict__ X, long n, long p, E& x) {
+  if constexpr (AOS) {
+    R* __restrict__ e = X + p * (long)E::SIZE;
+    each(x, [&](R& v, int f) { e[f] = v; });
+  } else {
+    each(x, [&](R& v, int f) { X[(long)f * n + p] = v; });
+  }
 }
 
 template <int N, class R> KF_DEV void store_sym(R* __restrict__ Po, long k, const R (&C)[N][N]) {
@@ -177,7 +198,7 @@ template <int N, int M, class P, bool TV = false> struct TreeTwoFilter {
 constexpr int kTreeBlock = 256;
 
 // Positions p of sequence blockIdx.y: build the elements.
-template <class Pipe>
+template <class Pipe, bool AOS>
 __global__ __launch_bounds__(kTreeBlock) void k_tree_build(TreeIO<typename Pipe::R> io,
                                                           typename Pipe::R* X) {
   using E = typename Pipe::E;
@@ -186,7 +207,7 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_build(TreeIO<typename Pipe:
   if (p >= io.Tp) return;
   Pipe pp(io, seq);
   E e = pp.element(p);
-  soa_store(X + seq * E::SIZE * io.Tp, io.Tp, p, e);
+  elem_store<AOS>(X + seq * E::SIZE * io.Tp, io.Tp, p, e);
 }
 
 // Algorithm 1, one level with offset s over a level of n positions:
@@ -200,13 +221,13 @@ __global__ __launch_bounds__(kTreeBlock) void k_hs_level(const typename Pipe::R*
   if (p >= n) return;
   const long off = seq * E::SIZE * n;
   E b;
-  soa_load(b, Xin + off, n, p);
+  elem_load<false>(b, Xin + off, n, p);
   if (p >= s) {
     E a;
-    soa_load(a, Xin + off, n, p - s);
+    elem_load<false>(a, Xin + off, n, p - s);
     b = Pipe::op(a, b);
   }
-  soa_store(Xout + off, n, p, b);
+  elem_store<false>(Xout + off, n, p, b);
 }
 
 // Up-sweep level with offset s, shared by Algorithms 2 and 3: the i-th active
@@ -222,10 +243,10 @@ __global__ __launch_bounds__(kTreeBlock) void k_bl_up(TreeIO<typename Pipe::R> i
   if (k >= io.Tp) return;
   typename Pipe::R* x = X + seq * E::SIZE * io.Tp;
   E a, b;
-  soa_load(a, x, io.Tp, k - s);
-  soa_load(b, x, io.Tp, k);
+  elem_load<true>(a, x, io.Tp, k - s);
+  elem_load<true>(b, x, io.Tp, k);
   b = Pipe::op(a, b);
-  soa_store(x, io.Tp, k, b);
+  elem_store<true>(x, io.Tp, k, b);
 }
 
 // Algorithm 2: the root takes the neutral element.
@@ -235,7 +256,7 @@ __global__ void k_bl_root(TreeIO<typename Pipe::R> io, typename Pipe::R* X) {
   if (threadIdx.x != 0) return;
   E e;
   set_identity(e);
-  soa_store(X + (long)blockIdx.y * E::SIZE * io.Tp, io.Tp, io.Tp - 1, e);
+  elem_store<true>(X + (long)blockIdx.y * E::SIZE * io.Tp, io.Tp, io.Tp - 1, e);
 }
 
 // Algorithm 2, down-sweep level with offset s: t = X[k - s]; X[k - s] = X[k];
@@ -250,11 +271,11 @@ __global__ __launch_bounds__(kTreeBlock) void k_bl_down(TreeIO<typename Pipe::R>
   if (k >= io.Tp) return;
   typename Pipe::R* x = X + seq * E::SIZE * io.Tp;
   E l, r;
-  soa_load(l, x, io.Tp, k - s);
-  soa_load(r, x, io.Tp, k);
-  soa_store(x, io.Tp, k - s, r);
+  elem_load<true>(l, x, io.Tp, k - s);
+  elem_load<true>(r, x, io.Tp, k);
+  elem_store<true>(x, io.Tp, k - s, r);
   r = Pipe::op(r, l);
-  soa_store(x, io.Tp, k, r);
+  elem_store<true>(x, io.Tp, k, r);
 }
 
 // Algorithm 3, down-sweep level with offset s: for m = 1, 2, ... the paper's
@@ -272,10 +293,10 @@ __global__ __launch_bounds__(kTreeBlock) void k_lf_down(TreeIO<typename Pipe::R>
   if (j >= io.Tp) return;
   typename Pipe::R* x = X + seq * E::SIZE * io.Tp;
   E a, b;
-  soa_load(a, x, io.Tp, i);
-  soa_load(b, x, io.Tp, j);
+  elem_load<true>(a, x, io.Tp, i);
+  elem_load<true>(b, x, io.Tp, j);
   b = Pipe::op(a, b);
-  soa_store(x, io.Tp, j, b);
+  elem_store<true>(x, io.Tp, j, b);
 }
 
 // Algorithm 4, reduce pass: hi[i] = lo[2i] (x) lo[2i+1] (0-based; the paper's
@@ -289,10 +310,10 @@ __global__ __launch_bounds__(kTreeBlock) void k_sg_reduce(const typename Pipe::R
   if (i >= nhi) return;
   const typename Pipe::R* l = lo + seq * E::SIZE * nlo;
   E a, b;
-  soa_load(a, l, nlo, 2 * i);
-  soa_load(b, l, nlo, 2 * i + 1);
+  elem_load<false>(a, l, nlo, 2 * i);
+  elem_load<false>(b, l, nlo, 2 * i + 1);
   a = Pipe::op(a, b);
-  soa_store(hi + seq * E::SIZE * nhi, nhi, i, a);
+  elem_store<false>(hi + seq * E::SIZE * nhi, nhi, i, a);
 }
 
 // Algorithm 4, down-sweep into a level of nlo positions from the scanned level
@@ -310,20 +331,20 @@ __global__ __launch_bounds__(kTreeBlock) void k_sg_down(const typename Pipe::R* 
   typename Pipe::R* l = lo + seq * E::SIZE * nlo;
   E a;
   if (i & 1) {
-    soa_load(a, h, nhi, (i - 1) / 2);
+    elem_load<false>(a, h, nhi, (i - 1) / 2);
   } else {
     E b;
-    soa_load(a, h, nhi, i / 2 - 1);
-    soa_load(b, l, nlo, i);
+    elem_load<false>(a, h, nhi, i / 2 - 1);
+    elem_load<false>(b, l, nlo, i);
     a = Pipe::op(a, b);
   }
-  soa_store(l, nlo, i, a);
+  elem_store<false>(l, nlo, i, a);
 }
 
 // Outputs of positions p < T from the scan result (a level of n positions):
 // inclusive as it stands, or exclusive (Blelloch) combined with the element
 // rebuilt from the inputs.
-template <class Pipe, bool EXCLUSIVE>
+template <class Pipe, bool EXCLUSIVE, bool AOS>
 __global__ __launch_bounds__(kTreeBlock) void k_tree_extract(TreeIO<typename Pipe::R> io,
                                                             const typename Pipe::R* X, long n) {
   using E = typename Pipe::E;
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(kTreeBlock) void k_tree_extract(TreeIO<typename Pip
   if (p >= io.T) return;
   Pipe pp(io, seq);
   E s;
-  soa_load(s, X + seq * E::SIZE * n, n, p);
+  elem_load<AOS>(s, X + seq * E::SIZE * n, n, p);
   if (EXCLUSIVE) s = Pipe::op(s, pp.element(p));
   pp.extract(p, s);
 }
@@ -439,12 +460,14 @@ void tree_scan(TreeIO<typename Pipe::R> io, int scan, long nseq, typename Pipe::
   auto ptr = [&](const TreeArray& a) {
     return (a.buf ? X1 : X0) + a.pos * nseq * (long)E::SIZE;
   };
+  const bool aos = scan == KF_SCAN_BLELLOCH || scan == KF_SCAN_LADNER_FISCHER;
   for (const TreeStep& t : tree_plan(scan, io.T)) {
     if (t.threads <= 0) continue;
     const dim3 g = grid(t.threads), b(kTreeBlock);
     switch (t.kind) {
       case TK_BUILD:
-        hipLaunchKernelGGL((k_tree_build<Pipe>), g, b, 0, st, io, ptr(t.out));
+        if (aos) hipLaunchKernelGGL((k_tree_build<Pipe, true>), g, b, 0, st, io, ptr(t.out));
+        else hipLaunchKernelGGL((k_tree_build<Pipe, false>), g, b, 0, st, io, ptr(t.out));
         break;
       case TK_HS:
         hipLaunchKernelGGL((k_hs_level<Pipe>), g, b, 0, st, (const R*)ptr(t.in), ptr(t.out),
@@ -472,12 +495,16 @@ void tree_scan(TreeIO<typename Pipe::R> io, int scan, long nseq, typename Pipe::
                            ptr(t.out), t.out.n);
         break;
       case TK_EXTRACT:
-        hipLaunchKernelGGL((k_tree_extract<Pipe, false>), g, b, 0, st, io, (const R*)ptr(t.in),
-                           t.in.n);
+        if (aos)
+          hipLaunchKernelGGL((k_tree_extract<Pipe, false, true>), g, b, 0, st, io,
+                             (const R*)ptr(t.in), t.in.n);
+        else
+          hipLaunchKernelGGL((k_tree_extract<Pipe, false, false>), g, b, 0, st, io,
+                             (const R*)ptr(t.in), t.in.n);
         break;
-      case TK_EXTRACT_EXCL:
-        hipLaunchKernelGGL((k_tree_extract<Pipe, true>), g, b, 0, st, io, (const R*)ptr(t.in),
-                           t.in.n);
+      case TK_EXTRACT_EXCL:  // Blelloch only
+        hipLaunchKernelGGL((k_tree_extract<Pipe, true, true>), g, b, 0, st, io,
+                           (const R*)ptr(t.in), t.in.n);
         break;
     }
   }
