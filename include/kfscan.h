@@ -150,8 +150,9 @@ typedef struct kf_batch {
  *   H, R [T][ny][nx], [T][ny][ny]   H_{j+1}, R_{j+1}: y_{j+1} = H x_{j+1} + d + r
  *   d    [T][ny]       d_{j+1}, or NULL for zero offsets
  * The elements are built step by step from these arrays (eqs. pkf_init1..3,
- * prts_init1..2 with u, d) and scanned with the look-back scans over full
- * elements; the one-kernel-per-level scans are not offered (KF_ERR_UNSUPPORTED). */
+ * prts_init1..2 with u, d).  KF_SCAN_AUTO and _LOOKBACK select the look-back
+ * scan over full elements (_LOOKBACK_GENERIC); every other kf_scan is used as
+ * asked (the one-kernel-per-level scans with nseq <= 65535). */
 typedef struct kf_tv_problem {
     int32_t nx, ny, precision, scan;       /* any kf_scan                       */
     int64_t T;                             /* steps per sequence, >= 1          */
