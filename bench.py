@@ -388,16 +388,24 @@ def bench_batched(args, np, torch, W, kfscan, dev) -> int:
 
 
 def bench_serving(args, np, torch, W, kfscan, dev) -> int:
-    """Serving: jobs arrive as a Poisson process; whenever the GPU is free, every
-    job that has arrived is dispatched as one ragged batch (filter + RTS, a model
-    per job, kf_smooth_rts_batch).  Jobs: T = round(2^U), U ~ U[10, 16], nx = 4,
-    ny = 2, random stable F (rho = 0.98), Q = 0.05 I, H Gaussian, R = 0.2 I, FP32.
-    Inputs and outputs stay resident on the GPU; a dispatch uploads only the
-    jobs' lengths, rows and model indices.  First the saturated rate is measured
-    (all jobs in batches of up to 256), then arrivals at 0.5, 0.8 and 0.95 of it;
-    latency = time the host sees the job's batch finished - arrival time.  The
-    survey's serving workload has nx = 16, which is not built; this runs the
-    same protocol at nx = 4."""
+    """Serving: jobs arrive as a Poisson process and are dispatched as ragged
+    batches (filter + RTS, a model per job, kf_smooth_rts_batch).  Jobs:
+    T = round(2^U), U ~ U[10, 16], nx = 4, ny = 2, random stable F
+    (rho = 0.98), Q = 0.05 I, H Gaussian, R = 0.2 I, FP32.  Inputs and outputs
+    stay resident on the GPU; a dispatch uploads only the jobs' lengths, rows
+    and model indices.
+
+    Admission: with one stream, every job that has arrived is dispatched as one
+    batch whenever the GPU is free.  With two streams (each with its own
+    workspace), the jobs that arrive while a batch runs are dispatched at once
+    on the other stream and run beside it; a stream takes a new batch when its
+    previous one has finished.  First the saturated rate is measured (all jobs
+    in batches of up to 256), then arrivals at 0.5, 0.8 and 0.95 of it, for one
+    and for two streams; latency = time the host sees the job's batch finished
+    - arrival time.  Last, plain per-sequence FP64 calls (kf_smooth_rts, one
+    launch sequence per job) are timed on a sample of the jobs, with the
+    batched FP32 results' distance from them.  The survey's serving workload
+    has nx = 16, which is not built; this runs the same protocol at nx = 4."""
     prec = args.precision
     dt = kfscan.dtype_for(prec)
     rng = np.random.default_rng(args.seed)
@@ -412,80 +420,119 @@ def bench_serving(args, np, torch, W, kfscan, dev) -> int:
     dm_all = [torch.as_tensor(np.stack([m.arrays()[j] for m in models])).to(dev, dt).contiguous()
               for j in range(6)]
     yd = torch.as_tensor(y).to(dev, dt).contiguous()
-    del y
+    y64 = y
     Td_all = torch.as_tensor(lengths).to(dev)
     rows_all = torch.as_tensor(rows).to(dev)
     outs = {k: torch.empty(shape, dtype=dt, device=dev) for k, shape in
             (("m_filt", (total, 4)), ("P_filt", (total, 4, 4)), ("m_smooth", (total, 4)),
              ("P_smooth", (total, 4, 4)))}
     max_batch = 256
-    # one workspace sized for the largest possible batch
+    # one workspace per stream, sized for the largest possible batch
     probe = kfscan.KfBatch()
     probe.nx, probe.ny, probe.precision, probe.scan = 4, 2, kfscan.PRECISIONS[prec], 0
     probe.nseq, probe.nmodels, probe.total_steps = max_batch, max_batch, total
-    ws = torch.empty(kfscan.batch_workspace_size(probe), dtype=torch.uint8, device=dev)
+    wsize = kfscan.batch_workspace_size(probe)
+    streams = [torch.cuda.current_stream(dev), torch.cuda.Stream(dev)]
+    wss = [torch.empty(wsize, dtype=torch.uint8, device=dev) for _ in streams]
 
-    def dispatch(idx):
-        idx_d = torch.as_tensor(np.asarray(idx, dtype=np.int64)).to(dev, non_blocking=False)
-        mods = [t.index_select(0, idx_d).contiguous() for t in dm_all]
-        b = kfscan.KfBatch()
-        b.nx, b.ny, b.precision, b.scan = 4, 2, kfscan.PRECISIONS[prec], 0
-        b.nseq, b.nmodels, b.total_steps = len(idx), len(idx), total
-        Tb = Td_all.index_select(0, idx_d).contiguous()
-        ob = rows_all.index_select(0, idx_d).contiguous()
-        b.T, b.offset = Tb.data_ptr(), ob.data_ptr()
-        b.F, b.Q, b.H, b.R, b.m0, b.P0 = (t.data_ptr() for t in mods)
-        b.y = yd.data_ptr()
-        b.m_filt, b.P_filt = outs["m_filt"].data_ptr(), outs["P_filt"].data_ptr()
-        b.m_smooth, b.P_smooth = outs["m_smooth"].data_ptr(), outs["P_smooth"].data_ptr()
-        kfscan.run_batch("kf_smooth_rts_batch", b, dev, ws)
-        ev = torch.cuda.Event()
-        ev.record()
-        return ev, (mods, Tb, ob)
+    def dispatch(idx, slot):
+        with torch.cuda.stream(streams[slot]):
+            idx_d = torch.as_tensor(np.asarray(idx, dtype=np.int64)).to(dev, non_blocking=False)
+            mods = [t.index_select(0, idx_d).contiguous() for t in dm_all]
+            b = kfscan.KfBatch()
+            b.nx, b.ny, b.precision, b.scan = 4, 2, kfscan.PRECISIONS[prec], 0
+            b.nseq, b.nmodels, b.total_steps = len(idx), len(idx), total
+            Tb = Td_all.index_select(0, idx_d).contiguous()
+            ob = rows_all.index_select(0, idx_d).contiguous()
+            b.T, b.offset = Tb.data_ptr(), ob.data_ptr()
+            b.F, b.Q, b.H, b.R, b.m0, b.P0 = (t.data_ptr() for t in mods)
+            b.y = yd.data_ptr()
+            b.m_filt, b.P_filt = outs["m_filt"].data_ptr(), outs["P_filt"].data_ptr()
+            b.m_smooth, b.P_smooth = outs["m_smooth"].data_ptr(), outs["P_smooth"].data_ptr()
+            kfscan.run_batch("kf_smooth_rts_batch", b, dev, wss[slot])
+            ev = torch.cuda.Event()
+            ev.record()
+        return ev, (mods, Tb, ob, idx_d)
 
-    # saturated rate: all jobs, back to back, batches of max_batch
-    for _ in range(2):
-        dispatch(list(range(min(n, max_batch))))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    keep = []
-    for s0 in range(0, n, max_batch):
-        keep.append(dispatch(list(range(s0, min(n, s0 + max_batch)))))
-    torch.cuda.synchronize()
-    sat_s = time.perf_counter() - t0
+    def saturated(nstreams):
+        for _ in range(2):
+            for slot in range(nstreams):
+                dispatch(list(range(min(n, max_batch))), slot)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep = []
+        for j, s0 in enumerate(range(0, n, max_batch)):
+            keep.append(dispatch(list(range(s0, min(n, s0 + max_batch))), j % nstreams))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    sat = {ns: saturated(ns) for ns in (1, 2)}
+    sat_s = sat[1]
     sat_jobs = n / sat_s
-    if kfscan.workspace_status(ws):
-        raise RuntimeError("serving: a batch entry was refused")
-    results = []
-    for frac in (0.5, 0.5, 0.8, 0.95):   # the first run warms the allocator and is dropped
+    for w in wss:
+        if kfscan.workspace_status(w):
+            raise RuntimeError("serving: a batch entry was refused")
+
+    def poisson(frac, nstreams):
         arrivals = W.poisson_arrivals(n, frac * sat_jobs, np.random.default_rng(args.seed + 1))
         done_at = np.zeros(n)
         nxt = 0
-        inflight = None
+        inflight = [None] * nstreams
         batches = 0
         t0 = time.perf_counter()
         while True:
             now = time.perf_counter() - t0
-            if inflight is not None and inflight[0].query():
-                done_at[inflight[2]] = time.perf_counter() - t0
-                inflight = None
-            if inflight is None:
-                hi = int(np.searchsorted(arrivals, now, side="right"))
-                if hi > nxt:
-                    idx = list(range(nxt, min(hi, nxt + max_batch)))
-                    ev, hold = dispatch(idx)
-                    inflight = (ev, hold, idx)
-                    nxt = idx[-1] + 1
-                    batches += 1
-                elif nxt >= n:
-                    break
+            for slot in range(nstreams):
+                f = inflight[slot]
+                if f is not None and f[0].query():
+                    done_at[f[2]] = time.perf_counter() - t0
+                    inflight[slot] = None
+            free = [slot for slot in range(nstreams) if inflight[slot] is None]
+            hi = int(np.searchsorted(arrivals, now, side="right"))
+            if free and hi > nxt:
+                idx = list(range(nxt, min(hi, nxt + max_batch)))
+                ev, hold = dispatch(idx, free[0])
+                inflight[free[0]] = (ev, hold, idx)
+                nxt = idx[-1] + 1
+                batches += 1
+            elif nxt >= n and all(f is None for f in inflight):
+                break
         lat = (done_at - arrivals) * 1e3
-        results.append({"load": frac, "rate_jobs_per_s": frac * sat_jobs,
-                        "p50_ms": float(np.percentile(lat, 50)),
-                        "p99_ms": float(np.percentile(lat, 99)),
-                        "mean_batch": n / batches,
-                        "steps_per_s": total / (done_at.max() - arrivals[0])})
-    results = results[1:]
+        return {"load": frac, "streams": nstreams, "rate_jobs_per_s": frac * sat_jobs,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_batch": n / batches,
+                "steps_per_s": total / (done_at.max() - arrivals[0])}
+
+    poisson(0.5, 2)                      # warms the allocator on both streams; dropped
+    results = [poisson(frac, ns) for ns in (1, 2) for frac in (0.5, 0.8, 0.95)]
+    torch.cuda.synchronize()
+
+    # plain per-sequence FP64 launches on a sample of the jobs
+    sample = list(range(0, n, max(1, n // 100)))
+    d64 = [[torch.as_tensor(np.ascontiguousarray(a)).to(dev, torch.float64).contiguous()
+            for a in models[i].arrays()] for i in sample]
+    y64d = [torch.as_tensor(y64[rows[i]:rows[i] + lengths[i]]).to(dev, torch.float64).contiguous()
+            for i in sample]
+    ws64 = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    for j in range(2):                   # warm-up
+        kfscan.smooth_rts(d64[j], y64d[j], precision="f64", workspace=ws64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res64 = [kfscan.smooth_rts(d64[j], y64d[j], precision="f64", workspace=ws64)
+             for j in range(len(sample))]
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    steps64 = int(sum(lengths[i] for i in sample))
+    dist = 0.0
+    for j, i in enumerate(sample):
+        ref = res64[j][2].cpu().numpy()
+        g = outs["m_smooth"][rows[i]:rows[i] + lengths[i]].double().cpu().numpy()
+        dist = max(dist, float(np.max(np.abs(g - ref)) / np.max(np.abs(ref))))
+    fp64_plain = {"jobs": len(sample), "steps": steps64, "steps_per_s": steps64 / t64,
+                  "batched_fp32_steps_per_s": total / sat_s,
+                  "batched_fp32_m_smooth_rel_diff": dist}
+    del y64
+
     errors = None
     if args.cpu_seconds > 0:
         import oracle
@@ -507,7 +554,9 @@ def bench_serving(args, np, torch, W, kfscan, dev) -> int:
         "config": {"workload": "serving_%d_jobs_T2^U10-16_nx4_ny2" % n, "jobs": n,
                    "total_steps": total, "max_batch": max_batch, "seed": args.seed},
         "saturated_jobs_per_s": sat_jobs,
+        "saturated_jobs_per_s_two_streams": n / sat[2],
         "poisson": results,
+        "fp64_per_sequence": fp64_plain,
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))
