@@ -105,7 +105,7 @@ typedef enum kf_scan {
 /* The one-kernel-per-level scans (_BLELLOCH, _HILLIS_STEELE, _LADNER_FISCHER,
  * _SENGUPTA_A, _SENGUPTA_B) keep every element in the workspace (Hillis-
  * Steele and Sengupta need two such arrays) and are offered for kf_problem and
- * kf_tv_problem with nseq <= 65535, not for ragged batches. */
+ * kf_tv_problem with nseq <= 65535 and T <= 2^36, not for ragged batches. */
 
 typedef struct kf_problem {
     int32_t nx;            /* state dimension n   (see kf_supported)              */

@@ -53,8 +53,9 @@ static kf_status check_sizes(const kf_problem* p) {
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
   if (s != KF_OK) return s;
-  // the tree scans put sequences on the grid's y dimension
-  if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
+  // the tree scans put sequences on the grid's y dimension and positions on x
+  if (is_tree_scan(p->scan) && (p->nseq > 65535 || p->T > (int64_t(1) << 36)))
+    return KF_ERR_UNSUPPORTED;
   return check_layout(job_of(*p));
 }
 
@@ -75,7 +76,8 @@ static kf_status check_tv(const kf_tv_problem* p) {
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
   if (s != KF_OK) return s;
-  if (is_tree_scan(p->scan) && p->nseq > 65535) return KF_ERR_UNSUPPORTED;
+  if (is_tree_scan(p->scan) && (p->nseq > 65535 || p->T > (int64_t(1) << 36)))
+    return KF_ERR_UNSUPPORTED;
   return check_layout(job_of(*p));
 }
 

@@ -104,9 +104,10 @@ KF_DEV void pipelined(long n, Fetch&& fetch, Body&& body) {
 
 // Steps fetched ahead: four cover a memory round trip with the work of the
 // steps between; two when four sets of W scalars would not leave the step's
-// own arithmetic enough of the 256 architectural VGPRs.
+// own arithmetic enough of the 256 architectural VGPRs (FP64 arithmetic
+// needs twice the registers, so its sets get a smaller share).
 template <class R, int W> constexpr int seq_depth() {
-  return 4 * W * (int)(sizeof(R) / 4) <= 232 ? 4 : 2;
+  return 4 * W * (int)(sizeof(R) / 4) <= (sizeof(R) == 4 ? 232 : 128) ? 4 : 2;
 }
 
 // Loads of the per-step model with branch-free inputs: an absent u or d reads

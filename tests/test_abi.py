@@ -141,6 +141,7 @@ def test_tv_workspace_size_and_validation(kfscan):
     assert size(tvp(nx=5)) == 2
     assert size(tvp(scan=3)) == 0          # tree scans serve time-varying models too
     assert size(tvp(scan=3, nseq=70000)) == 2
+    assert size(tvp(scan=6, T=(1 << 36) + 1)) == 2
     p = tvp(T=100)
     for name in ("kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv"):
         assert getattr(lib, name)(ctypes.byref(p), None, 0, None) == 1   # null pointers
