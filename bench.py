@@ -404,8 +404,8 @@ def bench_serving(args, np, torch, W, kfscan, dev) -> int:
     and for two streams; latency = time the host sees the job's batch finished
     - arrival time.  Last, plain per-sequence FP64 calls (kf_smooth_rts, one
     launch sequence per job) are timed on a sample of the jobs, with the
-    batched FP32 results' distance from them.  The survey's serving workload
-    has nx = 16, which is not built; this runs the same protocol at nx = 4."""
+    batched FP32 results' distance from them.  The serving configuration this
+    protocol comes from has nx = 16, which is not built; this runs it at nx = 4."""
     prec = args.precision
     dt = kfscan.dtype_for(prec)
     rng = np.random.default_rng(args.seed)
