@@ -84,6 +84,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time for the oracle baseline (0 = skip)")
     ap.add_argument("--seed", type=int, default=20251110)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph replay measurement after the timed region")
     ap.add_argument("--workload", default="tracking",
                     choices=["tracking", "batched", "serving", "tv", "speedup", "scans"],
                     help="tracking: one long sequence (the headline); batched: 4096 ragged "
@@ -162,6 +164,27 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     events = [e for e in events if e is not None]
+
+    # the same pass captured once into a HIP graph and replayed K times (reported
+    # beside the headline, which times the passes as enqueued above)
+    graph_ms = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                one_pass()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) / K * 1e3
+        del g
 
     # device-copy reference: 256 MiB through the library's plain copy kernel,
     # timed with events (also the calibration dispatch of the counter runs)
@@ -256,6 +279,7 @@ def main() -> int:
                       kback: float(t_back.mean())},
         "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
         "copy_GBps": copy_gbps,
+        "graph_ms_per_step": graph_ms,
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))
