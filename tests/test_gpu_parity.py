@@ -209,3 +209,28 @@ def test_one_workspace_across_precisions_and_shapes():
                          mdl, yy, prec)
         for g, r in zip(out, ref):
             assert normwise(g.double().cpu().numpy(), r) <= TOL[prec]
+
+
+@pytest.mark.parametrize("scan", ["lookback", "lookback_generic", "sequential", "ladner_fischer",
+                                  "sengupta_b"])
+@pytest.mark.parametrize("entry", ["filter", "rts", "tf"])
+def test_many_short_equal_sequences(entry, scan):
+    """3000 sequences of 37 steps share the model in one kf_problem: one tile
+    per sequence for the look-back scans (the ticket -> sequence map), 47
+    blocks of 64 lanes for the sequential recursions, 3000 grid rows for the
+    tree scans.  Sampled sequences, including the first and the last, are
+    compared with the oracle."""
+    _say("many sequences", entry, scan)
+    rng = np.random.default_rng(37)
+    model = W.random_stable_model(4, 2, 0.95, 0.1, 0.5, rng)
+    nseq, T = 3000, 37
+    ys = np.stack([W.simulate(model, T, rng) for _ in range(nseq)])
+    k = kfscan()
+    out = {"filter": k.filter, "rts": k.smooth_rts, "tf": k.smooth_twofilter}[entry](
+        to_dev(model, "f64"), y_dev(ys, "f64"), precision="f64", scan=scan)
+    torch.cuda.synchronize()
+    out = [o.double().cpu().numpy() for o in out]
+    for s in (0, 1, 63, 64, 1500, 2998, 2999):
+        ref = _reference(entry, model, ys[s], "f64")
+        for g, r in zip(out, ref):
+            assert normwise(g[s], r) <= TOL["f64"], (entry, scan, s)
