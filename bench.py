@@ -352,6 +352,29 @@ def bench_batched(args, np, torch, W, kfscan, dev) -> int:
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     achieved = alg_bytes / (lat.mean() * 1e-3) / 1e9
 
+    # the same pass captured once into a HIP graph and replayed K times
+    graph_ms = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                one_pass()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) / K * 1e3
+        del g
+        for c in calls:
+            if kfscan.workspace_status(c[2]):
+                raise RuntimeError("batched workload: a batch entry was refused")
+
     cpu = None
     errors = None
     if args.cpu_seconds > 0:
@@ -405,6 +428,7 @@ def bench_batched(args, np, torch, W, kfscan, dev) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "whole pass"},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "graph_ms_per_step": graph_ms,
         "errors_vs_oracle": errors,
     }
     print(json.dumps(out))

@@ -58,3 +58,52 @@ def test_captured_pass_replays_match_eager(backward, scan):
         torch.cuda.synchronize()
         for a, b in zip(plan.outputs(), ref):
             assert torch.equal(a, b), (backward, scan, rep)
+
+
+def test_captured_ragged_batch_replays_match_eager():
+    """kf_smooth_rts_batch (prepare of one model per sequence, the device-side
+    tile map, both scans) captured once and replayed."""
+    import ctypes
+
+    from tests.test_gpu_batch import _case, _device_batch
+    _say("graph batch")
+    k = kfscan()
+    lib = k.load_library()
+    lengths = [5000, 300, 70000, 1, 2500, 9000, 777]
+    models, ys, offsets, total = _case(lengths, 4, 2, True, seed=41)
+    dm, yd, T, off = _device_batch(models, ys, offsets, total, True, "f32")
+    b, keep = k.make_batch(dm, yd, T, off, precision="f32", smoother=True)
+    ws = torch.empty(k.batch_workspace_size(b), dtype=torch.uint8, device="cuda")
+    outs = [keep[n] for n in ("m_filt", "P_filt", "m_smooth", "P_smooth")]
+
+    def call():
+        stream = torch.cuda.current_stream().cuda_stream
+        rc = lib.kf_smooth_rts_batch(ctypes.byref(b), ws.data_ptr(), ws.numel(), stream)
+        assert rc == 0
+
+    call()
+    torch.cuda.synchronize()
+    assert k.workspace_status(ws) == 0
+    ref = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        k.batch("filter", dm, yd, T, off, precision="f32")   # eager work in between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert k.workspace_status(ws) == 0
+        for a, r in zip(outs, ref):
+            # rows outside every sequence are not written by either run
+            a_n, r_n = a.cpu().numpy(), r.cpu().numpy()
+            for i, L in enumerate(lengths):
+                sl = slice(offsets[i], offsets[i] + L)
+                assert np.array_equal(a_n[sl], r_n[sl]), (rep, i)
