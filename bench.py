@@ -786,7 +786,6 @@ def bench_scans(args, np, torch, W, kfscan, dev) -> int:
     dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt).contiguous()  # noqa: E731
     full = [dv(a) for a in (model.F, model.Q, model.H, model.R, model.u, model.d)]
     m0, P0, yd = dv(model.m0), dv(model.P0), dv(y)
-    ws = torch.empty(1, dtype=torch.uint8, device=dev)
     table = []
     for T in Ts:
         arrs = [a[:T] for a in full]
@@ -812,7 +811,6 @@ def bench_scans(args, np, torch, W, kfscan, dev) -> int:
             print("[scans] T=%d %-15s PKF %.3f  PRTS %.3f  PTFS %.3f ms" %
                   (T, scan, row["PKF_ms"], row["PRTS_ms"], row["PTFS_ms"]), file=sys.stderr,
                   flush=True)
-    del ws
     best = min((r for r in table if r["T"] == max(Ts)), key=lambda r: r["PKF_ms"])
     out = {
         "metric": "time of one PKF / PRTS / PTFS call per scan algorithm (the paper's model)",
