@@ -9,12 +9,15 @@ s_k = a_1 (x) ... (x) a_k (Sec. II-B).  ``identity`` pads a series whose length 
 not a power of two, which the paper's algorithms assume (Sec. II opening).
 
 * ``sequential``      -- the definition: one left-to-right loop.
-* ``hillis_steele``   -- Algorithm 1.  Reading C13: the level loop runs for
-                         d = 0..log2(T)-1 (the last iteration of the printed
-                         range does nothing).
-* ``blelloch``        -- Algorithm 2 (up-sweep, zero the root, down-sweep,
-                         final pass with the saved input).
-* ``ladner_fischer``  -- Algorithm 3 (in place, inclusive).
+* ``hillis_steele``   -- Algorithm 1.  Reading C13: log2(T) rounds, distances
+                         1, 2, .., 2^(log2(T)-1) (a round at distance T would do
+                         nothing).
+* ``blelloch``        -- Algorithm 2 (pairwise reduction, the exclusive prefix
+                         pushed down the tree from the identity at the root, a
+                         last inclusive pass).
+* ``ladner_fischer``  -- Algorithm 3 (in place, inclusive: pairwise reduction,
+                         then each block total completed with the prefix that
+                         ends where the block begins).
 * ``sengupta``        -- Algorithm 4 with threshold ``N`` (N = 1 is "Sengupta A").
 * ``reverse(scan)``   -- the reversed all-prefix-sums s_k = a_k (x) ... (x) a_T of
                          Sec. II-B, by reversing the series and swapping the
@@ -31,10 +34,6 @@ def _pow2_at_least(T: int) -> int:
     return p
 
 
-def _log2(p: int) -> int:
-    return p.bit_length() - 1
-
-
 def sequential(a, op, identity=None):
     out = []
     acc = None
@@ -45,91 +44,116 @@ def sequential(a, op, identity=None):
 
 
 def hillis_steele(a, op, identity=None):
-    """Algorithm 1.  Works for any T (no padding needed)."""
-    T = len(a)
+    """Algorithm 1: log2(T) rounds; in the round with distance s every
+    position j >= s combines the value s places before it with its own, both
+    taken from the previous round.  Works for any T (no padding needed)."""
     cur = list(a)
-    step = 1
-    while step < T:
-        prev = list(cur)                    # b <- copy(a)
-        for i in range(0, T - step):        # 0-based: i = 1..T-2^d in the paper
-            j = i + step
-            cur[j] = op(prev[i], prev[j])
-        step *= 2
+    s = 1
+    while s < len(cur):
+        cur = cur[:s] + [op(cur[j - s], cur[j]) for j in range(s, len(cur))]
+        s *= 2
     return cur
 
 
+def _padded(a, identity):
+    return list(a) + [identity] * (_pow2_at_least(len(a)) - len(a))
+
+
+def _block_totals(x, op):
+    """Totals of the dyadic blocks of the power-of-two series x, found by
+    pairwise reduction (the up-sweep shared by Algorithms 2 and 3): a dict
+    {(lo, hi): x[lo] (x) ... (x) x[hi-1]} over the nodes of the balanced binary
+    tree on [0, len(x)).  One operator application per inner node."""
+    tot = {}
+
+    def node(lo, hi):
+        if hi - lo == 1:
+            v = x[lo]
+        else:
+            mid = (lo + hi) // 2
+            v = op(node(lo, mid), node(mid, hi))
+        tot[(lo, hi)] = v
+        return v
+
+    node(0, len(x))
+    return tot
+
+
 def blelloch(a, op, identity):
-    """Algorithm 2 on the series padded with ``identity`` to a power of two."""
+    """Algorithm 2 on the series padded with ``identity`` to a power of two.
+
+    After the pairwise reduction, the exclusive prefix is pushed down the
+    tree: a node that receives the prefix c of everything before it hands c to
+    its left child and c (x) (left child's total) to its right child, starting
+    from the identity at the root.  A last pass turns the exclusive prefix of
+    each position into the inclusive one."""
     T = len(a)
     if T == 0:
         return []
-    P = _pow2_at_least(T)
-    x = [None] + list(a) + [identity] * (P - T)      # 1-based storage x[1..P]
-    saved = list(x)                                   # b <- copy(a)
-    D = _log2(P)
-    for d in range(D):                                # up-sweep
-        for i in range(0, P, 2 ** (d + 1)):
-            j, k = i + 2 ** d, i + 2 ** (d + 1)
-            x[k] = op(x[j], x[k])
-    x[P] = identity                                   # a_T <- neutral element
-    for d in range(D - 1, -1, -1):                    # down-sweep
-        for i in range(0, P, 2 ** (d + 1)):
-            j, k = i + 2 ** d, i + 2 ** (d + 1)
-            t = x[j]
-            x[j] = x[k]
-            x[k] = op(x[k], t)
-    for i in range(1, P + 1):                         # final pass: exclusive -> inclusive
-        x[i] = op(x[i], saved[i])
-    return x[1:T + 1]
+    x = _padded(a, identity)
+    tot = _block_totals(x, op)
+    excl = [None] * len(x)
+
+    def push(lo, hi, c):
+        if hi - lo == 1:
+            excl[lo] = c
+            return
+        mid = (lo + hi) // 2
+        push(lo, mid, c)
+        push(mid, hi, op(c, tot[(lo, mid)]))
+
+    push(0, len(x), identity)
+    return [op(excl[i], x[i]) for i in range(T)]
 
 
 def ladner_fischer(a, op, identity):
-    """Algorithm 3 (in-place Ladner-Fischer) on the padded series."""
+    """Algorithm 3 (in-place Ladner-Fischer) on the padded series.
+
+    After the pairwise reduction, position k (1-based) holds the total of the
+    dyadic block that ends at k and has the length of k's lowest set bit.
+    That is already the inclusive prefix when the block starts at 1 (k a power
+    of two); every other position needs the inclusive prefix that ends where
+    its block begins, combined on the left, and that position is finished
+    earlier because it lies at a smaller index."""
     T = len(a)
     if T == 0:
         return []
-    P = _pow2_at_least(T)
-    x = [None] + list(a) + [identity] * (P - T)
-    D = _log2(P)
-    for d in range(D):                                # up-sweep
-        for i in range(0, P, 2 ** (d + 1)):
-            j, k = i + 2 ** d, i + 2 ** (d + 1)
-            x[k] = op(x[j], x[k])
-    for d in range(D - 1, -1, -1):                    # down-sweep
-        for i in range(2 ** (d + 1), P, 2 ** (d + 1)):
-            j = i + 2 ** d
-            x[j] = op(x[i], x[j])
-    return x[1:T + 1]
+    x = _padded(a, identity)
+    tot = _block_totals(x, op)
+    out = [None] * (len(x) + 1)          # out[k]: inclusive prefix ending at k (1-based)
+    for k in range(1, len(x) + 1):
+        width = k & -k
+        own = tot[(k - width, k)]
+        out[k] = own if k == width else op(out[k - width], own)
+    return out[1:T + 1]
 
 
 def sengupta(a, op, identity, N=1):
-    """Algorithm 4: reduce levels up to a series of length N, Hillis-Steele on
-    that level, then the down-sweep.  ``N`` is rounded to a power of two in
-    [1, padded T]."""
+    """Algorithm 4: pairwise reduction until at most N elements remain, the
+    Hillis-Steele scan on those, then expansion level by level.  ``N`` is
+    rounded to a power of two in [1, padded T].
+
+    Expansion of one level: with S the inclusive scan of the pairs
+    (x_0 (x) x_1, x_2 (x) x_3, ...), the prefix at the second element of pair i
+    is S_i, and at the first element it is S_{i-1} (x) x_{2i} (x_0 alone for
+    i = 0)."""
     T = len(a)
     if T == 0:
         return []
-    P = _pow2_at_least(T)
-    N = min(_pow2_at_least(max(1, int(N))), P)
-    dstar = _log2(P // N)
-    levels = [[None] + list(a) + [identity] * (P - T)]   # a^(0), 1-based
-    for d in range(1, dstar + 1):                        # reduce passes
-        prev = levels[d - 1]
-        cur = [None] * (P // 2 ** d + 1)
-        for i in range(1, P // 2 ** d + 1):
-            cur[i] = op(prev[2 * i - 1], prev[2 * i])
-        levels.append(cur)
-    top = levels[dstar]
-    levels[dstar] = [None] + hillis_steele(top[1:], op)  # scan of the top level
-    for d in range(dstar - 1, -1, -1):                   # down-sweep
-        cur, up = levels[d], levels[d + 1]
-        for i in range(1, P // 2 ** d + 1):
-            if i > 1:
-                if i % 2 == 1:
-                    cur[i] = op(up[(i - 1) // 2], cur[i])
-                else:
-                    cur[i] = up[i // 2]
-    return levels[0][1:T + 1]
+    x = _padded(a, identity)
+    N = min(_pow2_at_least(max(1, int(N))), len(x))
+
+    def scan_level(v):
+        if len(v) <= N:
+            return hillis_steele(v, op)
+        S = scan_level([op(v[2 * i], v[2 * i + 1]) for i in range(len(v) // 2)])
+        out = []
+        for i, s in enumerate(S):
+            out.append(v[0] if i == 0 else op(S[i - 1], v[2 * i]))
+            out.append(s)
+        return out
+
+    return scan_level(x)[:T]
 
 
 def reverse(scan):

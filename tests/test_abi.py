@@ -207,15 +207,13 @@ def _oracle_counts(name, T, N=None):
 @pytest.mark.parametrize("T", [1, 2, 3, 8, 100, 1024, 5000, 1 << 15, 100000])
 def test_scan_counts_match_the_oracle_algorithms(kfscan, T):
     """kf_scan_counts, read off the launch plan, equals the number of operator
-    applications of the oracle's Algorithms 1-4 on the same length.  The
-    GPU Blelloch rebuilds only the T real elements in its final pass, the
-    oracle all P padded ones."""
-    P = 1 << max(0, (T - 1).bit_length())
+    applications of the oracle's Algorithms 1-4 on the same length (both
+    Blelloch versions finish only the T real positions in their last pass)."""
     assert kfscan.scan_counts("hillis_steele", T)[0] == _oracle_counts("hillis_steele", T)
     assert kfscan.scan_counts("ladner_fischer", T)[0] == _oracle_counts("ladner_fischer", T)
     assert kfscan.scan_counts("sengupta_a", T)[0] == _oracle_counts("sengupta", T, 1)
     assert kfscan.scan_counts("sengupta_b", T)[0] == _oracle_counts("sengupta", T, 16384)
-    assert kfscan.scan_counts("blelloch", T)[0] == _oracle_counts("blelloch", T) - (P - T)
+    assert kfscan.scan_counts("blelloch", T)[0] == _oracle_counts("blelloch", T)
 
 
 @pytest.mark.parametrize("T", [2, 16, 1024, 1 << 20])
