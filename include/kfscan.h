@@ -33,8 +33,24 @@
  *   P_filt, P_smooth : [nseq][T][nx][nx]      (exactly symmetric on output)
  * Q, R, P0 must be symmetric positive semi-definite with H Q H^T + R and the
  * predicted covariances positive definite (the smoothers factorise
- * F P_{k|k} F^T + Q).  The library does not inspect values: a numerical
- * breakdown produces non-finite outputs, never an error code.
+ * F P_{k|k} F^T + Q).
+ *
+ * Numerical failures never abort a call.  A breakdown of a factorisation --
+ * a non-positive Cholesky pivot of S_k (Sec. III-A) or of F P_{k|k} F^T + Q
+ * (eq. prts_init1), a zero pivot of I + C_i J_j (Lemma 1) or of I + P J
+ * (eq. cov_tf_combination) -- or a non-finite input makes that sequence's
+ * results non-finite; it does not touch the other sequences.  With the
+ * optional per-sequence status array (the `status` member of kf_problem,
+ * kf_batch and kf_tv_problem, device uint32 [nseq], or NULL), the whole-call
+ * entry points finish with a check of every output row: a sequence whose
+ * outputs hold a non-finite value gets KF_SEQ_NONFINITE and all its output
+ * rows overwritten with NaN; a ragged-batch entry that was skipped as invalid
+ * gets KF_SEQ_INVALID (its rows are not touched).  The array is written in
+ * full by every such call (no clearing needed) and is read after stream
+ * synchronisation; kf_workspace_status then also reports KF_WS_NUMERIC and
+ * returns KF_ERR_NUMERIC.  The check reads every output back once (about
+ * w (n + n^2) bytes per step per output pair) in three small kernels, which
+ * calls without a status array do not run.
  *
  * Workspace: device memory of at least kf_workspace_size() bytes, 256-byte
  * aligned, owned by the caller, with no initialisation required: the first
@@ -62,15 +78,26 @@
 extern "C" {
 #endif
 
-#define KFSCAN_ABI_VERSION 4
+#define KFSCAN_ABI_VERSION 5
 
 typedef enum kf_status {
     KF_OK = 0,
     KF_ERR_INVALID_ARG = 1,  /* null pointer, bad size, unknown enum value       */
     KF_ERR_UNSUPPORTED = 2,  /* (nx, ny) or precision/scan combination not built */
     KF_ERR_WORKSPACE = 3,    /* workspace too small or misaligned                */
-    KF_ERR_DEVICE = 4        /* the HIP runtime rejected a launch                */
+    KF_ERR_DEVICE = 4,       /* the HIP runtime rejected a launch                */
+    KF_ERR_NUMERIC = 5       /* kf_workspace_status: a sequence of the last call
+                                produced non-finite values (KF_WS_NUMERIC)       */
 } kf_status;
+
+/* Bits of the per-sequence status words (kf_problem::status etc.). */
+#define KF_SEQ_NONFINITE 1u  /* non-finite output (breakdown or bad input); all rows NaN */
+#define KF_SEQ_INVALID 2u    /* ragged batch: T[i] or offset[i] invalid, sequence skipped */
+
+/* Bits reported by kf_workspace_status. */
+#define KF_WS_TIMEOUT 1u     /* a look-back wait gave up                                  */
+#define KF_WS_INVALID 2u     /* a ragged batch held invalid entries                       */
+#define KF_WS_NUMERIC 4u     /* the status check found a sequence with non-finite outputs */
 
 typedef enum kf_precision {
     KF_PREC_F64 = 0,          /* FP64 storage and arithmetic                        */
@@ -118,6 +145,9 @@ typedef struct kf_problem {
     const void *y;                         /* measurements, device                  */
     void *m_filt, *P_filt;                 /* filter outputs, device                */
     void *m_smooth, *P_smooth;             /* smoother outputs, device (smoothers)  */
+    uint32_t *status;                      /* device [nseq] or NULL (see above)     */
+    int32_t items;                         /* 0, or steps per thread of the look-back
+                                              scans (2, 4, 8 or 16), see below     */
 } kf_problem;
 
 /* A batch of independent sequences of different lengths (Sec. IV applies to
@@ -140,6 +170,8 @@ typedef struct kf_batch {
     const void *y;                         /* device [total_steps][ny]               */
     void *m_filt, *P_filt;                 /* device [total_steps][nx], [..][nx][nx] */
     void *m_smooth, *P_smooth;             /* device, smoothers only                 */
+    uint32_t *status;                      /* device [nseq] or NULL                  */
+    int32_t items;                         /* 0, or steps per thread (see below)     */
 } kf_batch;
 
 /* A time-varying model with inputs (Sec. III-A with u, d; the model of the
@@ -162,7 +194,22 @@ typedef struct kf_tv_problem {
     const void *y;                         /* [nseq][T][ny], device             */
     void *m_filt, *P_filt;                 /* [nseq][T][nx], [nseq][T][nx][nx]  */
     void *m_smooth, *P_smooth;             /* smoothers only                    */
+    uint32_t *status;                      /* device [nseq] or NULL             */
+    int32_t items;                         /* 0, or steps per thread (see below) */
 } kf_tv_problem;
+
+/* Tile size of the look-back scans (`items` of kf_problem, kf_batch and
+ * kf_tv_problem).  A tile is 256 threads (nx <= 4) times `items` steps.  0
+ * lets the library choose (the time-invariant filter aims at one tile per
+ * CU, the scans over full elements take the longest tiles; a ragged batch
+ * always the longest); 2, 4, 8 or 16 asks for that many steps per thread in
+ * both scans of the call, capped at the longest each kernel is built for
+ * (16 for the time-invariant filter, 16 / 8 / 4 for the full-element scans at
+ * nx <= 2 / <= 4 / wider).  The wide-state scans (nx > 4) have one built tile
+ * size and ignore it.  Any other value is KF_ERR_INVALID_ARG.  Results do
+ * not depend on the tile size beyond rounding; a ragged batch keeps each
+ * sequence's results independent of the rest of the batch for any fixed
+ * value.  The autotuner of the Python package picks it per workload. */
 
 /* ABI version (KFSCAN_ABI_VERSION). */
 int kf_abi_version(void);
@@ -189,12 +236,15 @@ kf_status kf_workspace_clear(void *workspace, size_t bytes, void *stream);
 kf_status kf_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Diagnostic, synchronises `stream`: the error bits of the last call that
- * used this workspace, or-ed over its scans: bit 0, a look-back wait gave up
- * (see kf_workspace_timed_out); bit 1, a ragged batch held a sequence with
- * T[i] < 1 or rows outside [0, total_steps), or lengths adding up to more
- * than total_steps.  Such sequences (all of them in the last case) are skipped:
- * no kernel reads or writes their rows, and their outputs are left as they
- * were.  Needs at least the first 32 bytes of the workspace. */
+ * used this workspace, or-ed over its scans: KF_WS_TIMEOUT, a look-back wait
+ * gave up (see kf_workspace_timed_out); KF_WS_INVALID, a ragged batch held a
+ * sequence with T[i] < 1 or rows outside [0, total_steps), or lengths adding
+ * up to more than total_steps.  Such sequences (all of them in the last case)
+ * are skipped: no kernel reads or writes their rows, and their outputs are
+ * left as they were; KF_WS_NUMERIC, the call had a status array and some
+ * sequence's outputs held a non-finite value.  Returns KF_ERR_NUMERIC (with
+ * *status filled) when KF_WS_NUMERIC is set, else KF_OK.  Needs at least the
+ * first 32 bytes of the workspace. */
 kf_status kf_workspace_status(const void *workspace, size_t workspace_bytes, uint32_t *status,
                               void *stream);
 
@@ -273,6 +323,36 @@ kf_status kf_pass_filter(const kf_problem *p, void *workspace, size_t workspace_
 kf_status kf_pass_rts(const kf_problem *p, void *workspace, size_t workspace_bytes, void *stream);
 kf_status kf_pass_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
                             void *stream);
+
+/* ---- Self-test of the scan skeleton ------------------------------------
+ * The single-pass look-back drivers of the scans above (fold, wavefront scan,
+ * windowed decoupled look-back with anchors, step walk): group = 1 runs the
+ * thread driver of the nx <= 4 scans (256 threads x items steps per tile),
+ * group = 8 or 16 the group driver of the wide-state scans (groups of that
+ * many lanes, 256 / 128 threads, items steps per group), each with an exact,
+ * associative, non-commutative operator, so that its all-prefix-sums and
+ * reversed all-prefix-sums (Sec. II-B) can be compared bit for bit with a
+ * host scan.  An element is the affine map (A, b, C) acting on pairs (v, M)
+ * with v in Z_p^2, M in Z_p^{2x2}: v -> A v + b, M -> A M + C, mod p, where
+ * p = 33554393 for KF_PREC_F64 (values stored as float64) and p = 2039 for
+ * KF_PREC_F32 (float32).
+ *   elems  : device [nseq][T][10]: A row-major (4), b (2), C row-major (4),
+ *            integers in [0, p); element 0 (forward) or T-1 (reverse) of
+ *            each sequence must have A = 0, which anchors every prefix
+ *   states : device [nseq][T][6], written: (b, C) of the composed map
+ *            forward:  row k = a_1 then a_2 ... then a_{k+1}
+ *            reverse:  row k = a_T then a_{T-1} ... then a_{k+1}
+ *            (1-based a; the composition of a_i then a_j is
+ *             (A_j A_i, A_j b_i + b_j, A_j C_i + C_j))
+ * reverse is 0 or 1; items (2, 4, 8 or 16) is the steps per thread of the
+ * tiles (256 threads).  Values outside [0, p) give undefined results (never
+ * a fault).  The workspace (kf_selftest_scan_workspace bytes, 256-byte
+ * aligned) needs no initialisation.  Asynchronous on `stream`. */
+kf_status kf_selftest_scan_workspace(int32_t precision, int32_t group, int32_t items, int64_t T,
+                                     int64_t nseq, size_t *bytes);
+kf_status kf_selftest_scan(int32_t precision, int32_t group, int32_t reverse, int32_t items,
+                           int64_t T, int64_t nseq, const void *elems, void *states,
+                           void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

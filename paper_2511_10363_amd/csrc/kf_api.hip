@@ -24,12 +24,165 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
     dst[i] = src[i];
 }
 
+// ---------------------------------------------------------------------------
+// Per-sequence numeric status (the optional status array of a call).
+//
+// k_status_init writes every word: KF_SEQ_INVALID for a ragged-batch entry
+// that the scans skipped (the validity rule of k_batch_tiles: 1 <= T[i],
+// rows inside [0, total_steps), valid lengths adding up to at most
+// total_steps), else 0.  One block when the batch arrays are given, a
+// grid-stride fill otherwise.
+// k_status_check reads every output value of every valid sequence and raises
+// KF_SEQ_NONFINITE on a non-finite one (plus KF_WS_NUMERIC in the workspace's
+// error word); k_status_fill then overwrites every output value of such a
+// sequence with NaN.  Both walk (sequence, chunk) pairs grid-stride; a
+// sequence's values are one contiguous range per output array.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_status_init(const int64_t* __restrict__ len,
+                                                       const int64_t* __restrict__ row, long nseq,
+                                                       long total_steps,
+                                                       uint32_t* __restrict__ status) {
+  if (!len) {
+    for (long i = blockIdx.x * (long)BLOCK + threadIdx.x; i < nseq; i += (long)gridDim.x * BLOCK)
+      status[i] = 0u;
+    return;
+  }
+  __shared__ long long s_sum[BLOCK];
+  const int tid = threadIdx.x;
+  auto valid = [&](long i) {
+    const long T = (long)len[i], r = (long)row[i];
+    return T >= 1 && T <= total_steps && r >= 0 && r <= total_steps - T;
+  };
+  long long part = 0;
+  for (long i = tid; i < nseq; i += BLOCK)
+    if (valid(i)) part += (long long)len[i];
+  s_sum[tid] = part;
+  __syncthreads();
+  for (int o = BLOCK / 2; o > 0; o >>= 1) {
+    if (tid < o) s_sum[tid] += s_sum[tid + o];
+    __syncthreads();
+  }
+  const bool over = s_sum[0] > (long long)total_steps;
+  for (long i = tid; i < nseq; i += BLOCK)
+    status[i] = (over || !valid(i)) ? KF_SEQ_INVALID : 0u;
+}
+
+// Values of sequence q in one output array of `width` scalars per row.
+struct SeqRange {
+  long begin, count;
+};
+KF_DEV SeqRange seq_range(const int64_t* __restrict__ len, const int64_t* __restrict__ row,
+                          long T, long q, long width) {
+  if (len) return SeqRange{(long)row[q] * width, (long)len[q] * width};
+  return SeqRange{q * T * width, T * width};
+}
+
+template <class R> struct StatusArgs {
+  R* out[4];             // m_filt, P_filt, m_smooth, P_smooth (the last two may be null)
+  const int64_t* len;    // ragged batch (null for equal-length sequences)
+  const int64_t* row;
+  long T, nseq, chunks;  // chunks: blocks' worth of work per sequence
+  int nx;
+  uint32_t* status;
+  unsigned* ws_err;
+};
+
+template <class R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_status_check(StatusArgs<R> a) {
+  const long work = a.nseq * a.chunks;
+  for (long b = blockIdx.x; b < work; b += gridDim.x) {
+    const long q = b / a.chunks, c = b - q * a.chunks;
+    if (a.status[q] & KF_SEQ_INVALID) continue;
+    int bad = 0;
+#pragma unroll 1
+    for (int o = 0; o < 4; ++o) {
+      const R* __restrict__ p = a.out[o];
+      if (!p) continue;
+      const long width = (o & 1) ? (long)a.nx * a.nx : (long)a.nx;
+      const SeqRange rg = seq_range(a.len, a.row, a.T, q, width);
+      const long per = (rg.count + a.chunks - 1) / a.chunks;
+      const long lo = c * per, hi = (lo + per < rg.count) ? lo + per : rg.count;
+      for (long i = lo + threadIdx.x; i < hi; i += BLOCK) bad |= !__builtin_isfinite(p[rg.begin + i]);
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) {
+      atomicOr(a.status + q, KF_SEQ_NONFINITE);
+      atomicOr(a.ws_err, KF_WS_NUMERIC);
+    }
+  }
+}
+
+template <class R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_status_fill(StatusArgs<R> a) {
+  const long work = a.nseq * a.chunks;
+  const R nan = __builtin_nan("");
+  for (long b = blockIdx.x; b < work; b += gridDim.x) {
+    const long q = b / a.chunks, c = b - q * a.chunks;
+    if ((a.status[q] & (KF_SEQ_NONFINITE | KF_SEQ_INVALID)) != KF_SEQ_NONFINITE) continue;
+#pragma unroll 1
+    for (int o = 0; o < 4; ++o) {
+      R* __restrict__ p = a.out[o];
+      if (!p) continue;
+      const long width = (o & 1) ? (long)a.nx * a.nx : (long)a.nx;
+      const SeqRange rg = seq_range(a.len, a.row, a.T, q, width);
+      const long per = (rg.count + a.chunks - 1) / a.chunks;
+      const long lo = c * per, hi = (lo + per < rg.count) ? lo + per : rg.count;
+      for (long i = lo + threadIdx.x; i < hi; i += BLOCK) p[rg.begin + i] = nan;
+    }
+  }
+}
+
+template <class R>
+static kf_status enqueue_status(Op op, const Job& j, char* ws, const Layout& L, hipStream_t st) {
+  constexpr int B = 256;
+  const long nseq = j.nseq;
+  if (j.batch)
+    hipLaunchKernelGGL((k_status_init<1024>), dim3(1), dim3(1024), 0, st, j.len, j.row, nseq,
+                       j.total_steps, j.status);
+  else
+    hipLaunchKernelGGL((k_status_init<B>), dim3((unsigned)((nseq + B - 1) / B < 4096
+                                                               ? (nseq + B - 1) / B : 4096)),
+                       dim3(B), 0, st, (const int64_t*)nullptr, (const int64_t*)nullptr, nseq,
+                       j.total_steps, j.status);
+  StatusArgs<R> a{};
+  a.out[0] = static_cast<R*>(j.m_filt);
+  a.out[1] = static_cast<R*>(j.P_filt);
+  if (op != OP_FILTER) {
+    a.out[2] = static_cast<R*>(j.m_smooth);
+    a.out[3] = static_cast<R*>(j.P_smooth);
+  }
+  a.len = j.batch ? j.len : nullptr;
+  a.row = j.batch ? j.row : nullptr;
+  a.T = j.T;
+  a.nseq = nseq;
+  a.nx = j.nx;
+  // about 64K values of one output pair per (sequence, chunk), by the mean length
+  const long mean_rows = j.batch ? (j.total_steps + nseq - 1) / nseq : j.T;
+  long chunks = (mean_rows * (long)(j.nx + j.nx * j.nx) + 65535) / 65536;
+  a.chunks = chunks < 1 ? 1 : (chunks > 4096 ? 4096 : chunks);
+  a.status = j.status;
+  a.ws_err = reinterpret_cast<unsigned*>(ws + L.ctr[0]) + 2;
+  const long work = nseq * a.chunks;
+  const dim3 grid((unsigned)(work < 65536 ? work : 65536));
+  hipLaunchKernelGGL((k_status_check<R, B>), grid, dim3(B), 0, st, a);
+  hipLaunchKernelGGL((k_status_fill<R, B>), grid, dim3(B), 0, st, a);
+  return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+}
+
+bool wide_shape_built(int nx, int ny) {
+#define KFS_TEST(n, m) \
+  if (nx == n && ny == m) return true;
+  KFS_WIDE_SHAPES(KFS_TEST)
+#undef KFS_TEST
+  return false;
+}
+
 bool shape_built(int nx, int ny) {
 #define KFS_TEST(n, m) \
   if (nx == n && ny == m) return true;
   KFS_SHAPES(KFS_TEST)
 #undef KFS_TEST
-  return false;
+  return wide_shape_built(nx, ny);
 }
 
 static kf_status check_common(int nx, int ny, int precision, int scan) {
@@ -37,10 +190,16 @@ static kf_status check_common(int nx, int ny, int precision, int scan) {
   if (precision < KF_PREC_F64 || precision > KF_PREC_F32_F64SOLVE) return KF_ERR_INVALID_ARG;
   if (scan < KF_SCAN_AUTO || scan > KF_SCAN_SENGUPTA_B) return KF_ERR_INVALID_ARG;
   if (!shape_built(nx, ny)) return KF_ERR_UNSUPPORTED;
+  // wide states: the look-back scan over full elements only
+  if (is_wide(nx) && scan != KF_SCAN_AUTO && scan != KF_SCAN_LOOKBACK &&
+      scan != KF_SCAN_LOOKBACK_GENERIC)
+    return KF_ERR_UNSUPPORTED;
   return KF_OK;
 }
 
 static kf_status check_layout(const Job& j) {
+  if (j.items != 0 && j.items != 2 && j.items != 4 && j.items != 8 && j.items != 16)
+    return KF_ERR_INVALID_ARG;
   const Layout L = make_layout(j);
   if (L.grid[0] > 2147483647L || L.grid[1] > 2147483647L) return KF_ERR_INVALID_ARG;
   return KF_OK;
@@ -76,6 +235,7 @@ static kf_status check_tv(const kf_tv_problem* p) {
   if (p->T > (int64_t(1) << 40) || p->nseq > (int64_t(1) << 31)) return KF_ERR_INVALID_ARG;
   kf_status s = check_common(p->nx, p->ny, p->precision, p->scan);
   if (s != KF_OK) return s;
+  if (is_wide(p->nx)) return KF_ERR_UNSUPPORTED;
   if (is_tree_scan(p->scan) && (p->nseq > 65535 || p->T > (int64_t(1) << 36)))
     return KF_ERR_UNSUPPORTED;
   return check_layout(job_of(*p));
@@ -95,11 +255,16 @@ static kf_status run_job(Op op, int stages, const Job& j, void* ws, size_t ws_by
     return KF_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
+  kf_status s;
   switch (j.precision) {
-    case KF_PREC_F64: return run_f64(op, stages, j, w, L, st);
-    case KF_PREC_F32: return run_f32(op, stages, j, w, L, st);
-    default: return run_mixed(op, stages, j, w, L, st);
+    case KF_PREC_F64: s = run_f64(op, stages, j, w, L, st); break;
+    case KF_PREC_F32: s = run_f32(op, stages, j, w, L, st); break;
+    default: s = run_mixed(op, stages, j, w, L, st); break;
   }
+  // the status check follows whole calls only (the stage entry points leave it)
+  if (s != KF_OK || !j.status || stages != ST_ALL) return s;
+  return j.precision == KF_PREC_F64 ? enqueue_status<double>(op, j, w, L, st)
+                                    : enqueue_status<float>(op, j, w, L, st);
 }
 
 static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws_bytes,
@@ -107,6 +272,16 @@ static kf_status run(Op op, int stages, const kf_problem* p, void* ws, size_t ws
   kf_status s = check_sizes(p);
   if (s != KF_OK) return s;
   return run_job(op, stages, job_of(*p), ws, ws_bytes, stream);
+}
+
+kf_status run_problem(Op op, const kf_problem* p, void* ws, size_t ws_bytes, void* stream,
+                      size_t* ws_needed) {
+  kf_status s = check_sizes(p);
+  if (s != KF_OK) return s;
+  const size_t need = make_layout(job_of(*p)).total;
+  if (ws_needed) *ws_needed = need;
+  if (ws_bytes < need) return KF_ERR_WORKSPACE;
+  return run_job(op, ST_ALL, job_of(*p), ws, ws_bytes, stream);
 }
 
 static kf_status run_tv(Op op, const kf_tv_problem* p, void* ws, size_t ws_bytes, void* stream) {
@@ -149,6 +324,7 @@ const char* kf_status_string(kf_status s) {
     case KF_ERR_UNSUPPORTED: return "unsupported shape, precision or scan";
     case KF_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
     case KF_ERR_DEVICE: return "HIP launch failed";
+    case KF_ERR_NUMERIC: return "a sequence produced non-finite values";
   }
   return "unknown status";
 }
@@ -238,7 +414,7 @@ kf_status kf_workspace_status(const void* ws, size_t ws_bytes, uint32_t* status,
   kf_status s = kfs::read_error_words(ws, ws_bytes, words, stream);
   if (s != KF_OK) return s;
   *status = words[0] | words[1];
-  return KF_OK;
+  return (*status & KF_WS_NUMERIC) ? KF_ERR_NUMERIC : KF_OK;
 }
 
 kf_status kf_workspace_timed_out(const kf_problem* p, const void* ws, size_t ws_bytes,

@@ -2,6 +2,7 @@
 // per-precision translation units, which list the shapes that are built.
 #pragma once
 #include "kf_kernels.hpp"
+#include "kf_wide.hpp"
 #include "kf_seq.hpp"
 #include "kf_tree.hpp"
 #include "kf_plan.hpp"
@@ -126,7 +127,7 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
     });
     if (p.batch)
       hipLaunchKernelGGL((k_batch_tiles<1024>), dim3(1), dim3(1024), 0, st, p.len, p.row, p.nseq,
-                         p.total_steps, (long)kBlock * L.items[0], (long)kBlock * L.items[1],
+                         p.total_steps, L.tile[0], L.tile[1],
                          reinterpret_cast<int64_t*>(ws + L.tile_start[0]),
                          reinterpret_cast<int64_t*>(ws + L.tile_start[1]),
                          reinterpret_cast<int*>(ws + L.tile_map[0]),
@@ -224,6 +225,90 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
   return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
 }
 
+// States wider than nx = 4 (kf_wide.hpp): the look-back scans over
+// row-distributed elements, for equal-length sequences and ragged batches.
+template <int N, int M, class P>
+kf_status run_wide(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st) {
+  using R = typename P::R;
+  constexpr int B = wide_block(N);
+  constexpr int IL = wide_items(N);
+  R* cst = reinterpret_cast<R*>(ws + L.cst);
+  size_t prep_blocks = (L.ctrl_words + 255) / 256;
+  if (prep_blocks > 1024) prep_blocks = 1024;
+  if ((long)prep_blocks < p.nmodels) prep_blocks = (size_t)p.nmodels;
+  const long cst_stride = (p.batch && p.nmodels > 1) ? L.cst_stride : 0;
+  if (stages & ST_PREPARE) {
+    hipLaunchKernelGGL((k_wprepare<N, M, R>), dim3((unsigned)prep_blocks), dim3(256), 0, st,
+                       static_cast<const R*>(p.F), static_cast<const R*>(p.Q),
+                       static_cast<const R*>(p.H), static_cast<const R*>(p.R),
+                       static_cast<const R*>(p.m0), static_cast<const R*>(p.P0), cst,
+                       reinterpret_cast<unsigned*>(ws), L.ctrl_words, p.nmodels, L.cst_stride);
+    if (p.batch)
+      hipLaunchKernelGGL((k_batch_tiles<1024>), dim3(1), dim3(1024), 0, st, p.len, p.row, p.nseq,
+                         p.total_steps, L.tile[0], L.tile[1],
+                         reinterpret_cast<int64_t*>(ws + L.tile_start[0]),
+                         reinterpret_cast<int64_t*>(ws + L.tile_start[1]),
+                         reinterpret_cast<int*>(ws + L.tile_map[0]),
+                         reinterpret_cast<int*>(ws + L.tile_map[1]), L.grid[0], L.grid[1],
+                         reinterpret_cast<unsigned*>(ws + L.ctr[0]) + 2,
+                         reinterpret_cast<unsigned*>(ws + L.ctr[1]) + 2);
+  }
+  const R* y = static_cast<const R*>(p.y);
+  R* mf = static_cast<R*>(p.m_filt);
+  R* Pf = static_cast<R*>(p.P_filt);
+  R* ms = static_cast<R*>(p.m_smooth);
+  R* Ps = static_cast<R*>(p.P_smooth);
+  auto args = [&](int slot) {
+    ScanArgs<R> a{};
+    a.flags = reinterpret_cast<int*>(ws + L.flags[slot]);
+    a.agg = reinterpret_cast<u64*>(ws + L.agg[slot]);
+    a.pre = reinterpret_cast<u64*>(ws + L.pre[slot]);
+    a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
+    a.T = p.T;
+    a.ntiles = L.ntiles[slot];
+    a.nseq = p.nseq;
+    if (p.batch) {
+      a.tile_seq = reinterpret_cast<const int*>(ws + L.tile_map[slot]);
+      a.tile_start = reinterpret_cast<const int64_t*>(ws + L.tile_start[slot]);
+      a.seq_len = p.len;
+      a.seq_row = p.row;
+      a.cst_stride = cst_stride;
+    }
+    return a;
+  };
+  if (stages & ST_FORWARD)
+    hipLaunchKernelGGL((k_wfilter<N, M, P, B, IL>), dim3((unsigned)L.grid[0]), dim3(B), 0, st,
+                       args(0), cst, y, (const R*)nullptr, (const R*)nullptr, mf, Pf);
+  if (op != OP_FILTER && (stages & ST_BACKWARD)) {
+    if (op == OP_RTS)
+      hipLaunchKernelGGL((k_wrts<N, M, P, B, IL>), dim3((unsigned)L.grid[1]), dim3(B), 0, st,
+                         args(1), cst, y, (const R*)mf, (const R*)Pf, ms, Ps);
+    else
+      hipLaunchKernelGGL((k_wtwofilter<N, M, P, B, IL>), dim3((unsigned)L.grid[1]), dim3(B), 0,
+                         st, args(1), cst, y, (const R*)mf, (const R*)Pf, ms, Ps);
+  }
+  return hipGetLastError() == hipSuccess ? KF_OK : KF_ERR_DEVICE;
+}
+
+// Wide shapes compiled into the library (each in a translation unit of its
+// own, kf_wide_<precision>_<nx>.hip).
+#define KFS_WIDE_SHAPES(X) \
+  X(8, 4)                  \
+  X(16, 8)
+
+#define KFS_WIDE_EXTERN(n, m)                                                              \
+  extern template kf_status run_wide<n, m, PrecF64>(Op, int, const Job&, char*,           \
+                                                    const Layout&, hipStream_t);          \
+  extern template kf_status run_wide<n, m, PrecF32>(Op, int, const Job&, char*,           \
+                                                    const Layout&, hipStream_t);          \
+  extern template kf_status run_wide<n, m, PrecMixed>(Op, int, const Job&, char*,         \
+                                                      const Layout&, hipStream_t);
+KFS_WIDE_SHAPES(KFS_WIDE_EXTERN)
+#undef KFS_WIDE_EXTERN
+
+#define KFS_WIDE_INSTANTIATE(n, m, P)                                                      \
+  template kf_status run_wide<n, m, P>(Op, int, const Job&, char*, const Layout&, hipStream_t);
+
 // Shapes compiled into the library.
 #define KFS_SHAPES(X) \
   X(1, 1)             \
@@ -258,6 +343,10 @@ kf_status run_prec(Op op, int stages, const Job& p, char* ws, const Layout& L,
   if (p.nx == n && p.ny == m) return run_shape<n, m, P>(op, stages, p, ws, L, st);
   KFS_SHAPES(KFS_CASE)
 #undef KFS_CASE
+#define KFS_WCASE(n, m) \
+  if (p.nx == n && p.ny == m) return run_wide<n, m, P>(op, stages, p, ws, L, st);
+  KFS_WIDE_SHAPES(KFS_WCASE)
+#undef KFS_WCASE
   return KF_ERR_UNSUPPORTED;
 }
 

@@ -30,6 +30,16 @@ inline long ntiles_for(long T, int items) {
   return (T + tile - 1) / tile;
 }
 
+// States wider than nx = 4 are scanned by groups of nx lanes (kf_wide.hpp):
+// workgroups of wide_block(nx) threads, each group owning wide_items(nx)
+// steps, so a tile holds wide_block(nx) / nx * wide_items(nx) steps.  256
+// threads at nx = 8 (32 groups), 128 at nx = 16 (8 groups), whose LDS
+// scratch and look-back buffers then leave room for several workgroups per CU.
+inline bool is_wide(int nx) { return nx > 4; }
+constexpr int wide_block(int nx) { return nx <= 8 ? 256 : 128; }
+constexpr int wide_items(int) { return 16; }
+inline long wide_tile(int nx) { return (long)(wide_block(nx) / nx) * wide_items(nx); }
+
 inline int choose_items(long T, long nseq, int lmax, long target) {
   int L = lmax;
   while (L > 2 && nseq * ntiles_for(T, L) < target) L /= 2;
@@ -57,6 +67,7 @@ struct Layout {
   int items[2];               // steps per thread of the forward and backward scans
   long ntiles[2];             // tiles per sequence (equal-length sequences)
   long grid[2];               // blocks of the forward and backward scans
+  long tile[2];               // steps per tile of the forward and backward scans
   long cst_stride;            // scalars per model in the cst region
   size_t tile_start[2];       // ragged batch: first tile ticket of each sequence, int64 [nseq+1]
   size_t tile_map[2];         // ragged batch: sequence of each ticket, int32 [grid]
@@ -77,6 +88,8 @@ struct Job {
   void *m_filt, *P_filt, *m_smooth, *P_smooth;
   bool tv;                    // F, Q, H, R, u, d are per-step arrays
   const void *u, *d;          // time-varying model: may be null
+  uint32_t* status;           // per-sequence status words, device [nseq], or null
+  int items;                  // requested steps per thread (0 = the library's choice)
 };
 
 // The scans with one kernel launch per tree level (kf_tree.hpp).
@@ -100,6 +113,8 @@ inline Job job_of(const kf_problem& p) {
   j.F = p.F; j.Q = p.Q; j.H = p.H; j.R = p.R; j.m0 = p.m0; j.P0 = p.P0;
   j.y = p.y;
   j.m_filt = p.m_filt; j.P_filt = p.P_filt; j.m_smooth = p.m_smooth; j.P_smooth = p.P_smooth;
+  j.status = p.status;
+  j.items = p.items;
   return j;
 }
 
@@ -121,6 +136,8 @@ inline Job job_of(const kf_tv_problem& p) {
   j.tv = true;
   j.y = p.y;
   j.m_filt = p.m_filt; j.P_filt = p.P_filt; j.m_smooth = p.m_smooth; j.P_smooth = p.P_smooth;
+  j.status = p.status;
+  j.items = p.items;
   return j;
 }
 
@@ -141,6 +158,8 @@ inline Job job_of(const kf_batch& b) {
   j.F = b.F; j.Q = b.Q; j.H = b.H; j.R = b.R; j.m0 = b.m0; j.P0 = b.P0;
   j.y = b.y;
   j.m_filt = b.m_filt; j.P_filt = b.P_filt; j.m_smooth = b.m_smooth; j.P_smooth = b.P_smooth;
+  j.status = b.status;
+  j.items = b.items;
   return j;
 }
 
@@ -167,18 +186,33 @@ inline Layout make_layout(const Job& j) {
     L.total = 256;
     return L;
   }
-  // A ragged batch always takes the longest tiles, so that each sequence is
-  // tiled, scanned and rounded the same whatever else is in the batch.
-  const int lf = (scan == KF_SCAN_LOOKBACK_GENERIC) ? items_per_thread(j.nx) : items_ti(j.nx);
-  const int lb = items_per_thread(j.nx);
-  L.items[0] = j.batch ? lf
-                       : choose_items(T, nseq, lf,
-                                      scan == KF_SCAN_LOOKBACK_GENERIC ? kTilesScan : kTilesTi);
-  L.items[1] = j.batch ? lb : choose_items(T, nseq, lb, kTilesScan);
+  if (is_wide(j.nx)) {
+    // one tile size for both scans, batch or not
+    for (int s = 0; s < 2; ++s) {
+      L.items[s] = wide_items(j.nx);
+      L.tile[s] = wide_tile(j.nx);
+    }
+  } else {
+    // A ragged batch always takes the longest tiles, so that each sequence is
+    // tiled, scanned and rounded the same whatever else is in the batch.
+    const int lf = (scan == KF_SCAN_LOOKBACK_GENERIC) ? items_per_thread(j.nx) : items_ti(j.nx);
+    const int lb = items_per_thread(j.nx);
+    if (j.items > 0) {
+      // the caller's tile size, capped at the longest each kernel is built for
+      L.items[0] = j.items < lf ? j.items : lf;
+      L.items[1] = j.items < lb ? j.items : lb;
+    } else {
+      L.items[0] = j.batch ? lf
+                           : choose_items(T, nseq, lf,
+                                          scan == KF_SCAN_LOOKBACK_GENERIC ? kTilesScan : kTilesTi);
+      L.items[1] = j.batch ? lb : choose_items(T, nseq, lb, kTilesScan);
+    }
+    for (int s = 0; s < 2; ++s) L.tile[s] = (long)kBlock * L.items[s];
+  }
   for (int s = 0; s < 2; ++s) {
-    L.ntiles[s] = ntiles_for(T, L.items[s]);
+    L.ntiles[s] = (T + L.tile[s] - 1) / L.tile[s];
     // a ragged batch: sum over sequences of ceil(T_i / tile) <= nseq + total / tile
-    L.grid[s] = j.batch ? nseq + ntiles_for(j.total_steps, L.items[s]) : L.ntiles[s] * nseq;
+    L.grid[s] = j.batch ? nseq + (j.total_steps + L.tile[s] - 1) / L.tile[s] : L.ntiles[s] * nseq;
   }
   // CLB<N, M, L>::SIZE: the model quantities and two sets of aggregate tables
   const size_t cst_words = 10 * n * n + 4 * n * m + m * m + 2 * n + 2 * 16 * (size_t)(n * m) +
@@ -240,5 +274,11 @@ kf_status run_f64(Op op, int stages, const Job& p, char* ws, const Layout& L, hi
 kf_status run_f32(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st);
 kf_status run_mixed(Op op, int stages, const Job& p, char* ws, const Layout& L, hipStream_t st);
 bool shape_built(int nx, int ny);
+bool wide_shape_built(int nx, int ny);
+// A whole call on kf_problem (kf_api.hip): argument checks, then every stage
+// of `op` on `ws`; *ws_needed (if given) receives the workspace size the
+// problem needs, and KF_ERR_WORKSPACE is returned when ws_bytes is smaller.
+kf_status run_problem(Op op, const kf_problem* p, void* ws, size_t ws_bytes, void* stream,
+                      size_t* ws_needed);
 
 }  // namespace kfs

@@ -1,0 +1,6 @@
+// Launch code of the nx = 16 group scans for precision policy PrecMixed.
+#include "kf_inst.hpp"
+
+namespace kfs {
+KFS_WIDE_INSTANTIATE(16, 8, PrecMixed)
+}  // namespace kfs

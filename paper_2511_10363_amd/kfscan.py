@@ -24,7 +24,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkfscan.so")
 
-KF_OK, KF_ERR_INVALID_ARG, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE, KF_ERR_DEVICE = range(5)
+(KF_OK, KF_ERR_INVALID_ARG, KF_ERR_UNSUPPORTED, KF_ERR_WORKSPACE, KF_ERR_DEVICE,
+ KF_ERR_NUMERIC) = range(6)
+# per-sequence status bits (the optional ``status`` tensor of a call) and the
+# workspace error bits of workspace_status()
+KF_SEQ_NONFINITE, KF_SEQ_INVALID = 1, 2
+KF_WS_TIMEOUT, KF_WS_INVALID, KF_WS_NUMERIC = 1, 2, 4
 PRECISIONS = {"f64": 0, "f32": 1, "mixed": 2}
 SCANS = {"auto": 0, "lookback": 1, "blelloch": 2, "hillis_steele": 3, "lookback_generic": 4,
          "sequential": 5, "ladner_fischer": 6, "sengupta_a": 7, "sengupta_b": 8}
@@ -38,7 +43,8 @@ class KfProblem(ctypes.Structure):
                 ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
                 ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
                 ("m_filt", _VOIDP), ("P_filt", _VOIDP),
-                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP), ("status", _VOIDP),
+                ("items", ctypes.c_int32)]
 
 
 class KfBatch(ctypes.Structure):
@@ -49,7 +55,8 @@ class KfBatch(ctypes.Structure):
                 ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
                 ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
                 ("m_filt", _VOIDP), ("P_filt", _VOIDP),
-                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP), ("status", _VOIDP),
+                ("items", ctypes.c_int32)]
 
 
 class KfTvProblem(ctypes.Structure):
@@ -59,7 +66,8 @@ class KfTvProblem(ctypes.Structure):
                 ("F", _VOIDP), ("Q", _VOIDP), ("H", _VOIDP), ("R", _VOIDP),
                 ("u", _VOIDP), ("d", _VOIDP), ("m0", _VOIDP), ("P0", _VOIDP), ("y", _VOIDP),
                 ("m_filt", _VOIDP), ("P_filt", _VOIDP),
-                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP)]
+                ("m_smooth", _VOIDP), ("P_smooth", _VOIDP), ("status", _VOIDP),
+                ("items", ctypes.c_int32)]
 
 
 class KfScanError(RuntimeError):
@@ -74,7 +82,7 @@ EXPORTS = ("kf_abi_version", "kf_status_string", "kf_supported", "kf_workspace_s
            "kf_pass_twofilter", "kf_batch_workspace_size", "kf_filter_batch",
            "kf_smooth_rts_batch", "kf_smooth_twofilter_batch", "kf_workspace_status",
            "kf_tv_workspace_size", "kf_filter_tv", "kf_smooth_rts_tv", "kf_smooth_twofilter_tv",
-           "kf_scan_counts")
+           "kf_scan_counts", "kf_selftest_scan_workspace", "kf_selftest_scan")
 STAGES = ("kf_prepare", "kf_pass_filter", "kf_pass_rts", "kf_pass_twofilter")
 # When set (the tests set it), every call synchronises and checks the
 # workspace's look-back timeout flag.
@@ -118,6 +126,14 @@ def load_library(path: str = LIB_PATH):
         lib.kf_scan_counts.restype = ctypes.c_int
         lib.kf_scan_counts.argtypes = [ctypes.c_int32, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        lib.kf_selftest_scan_workspace.restype = ctypes.c_int
+        lib.kf_selftest_scan_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.c_int64, ctypes.c_int64,
+                                                   ctypes.POINTER(ctypes.c_size_t)]
+        lib.kf_selftest_scan.restype = ctypes.c_int
+        lib.kf_selftest_scan.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _VOIDP,
+                                         _VOIDP, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_device_copy.restype = ctypes.c_int
         lib.kf_device_copy.argtypes = [_VOIDP, _VOIDP, ctypes.c_size_t, _VOIDP]
         lib.kf_workspace_timed_out.restype = ctypes.c_int
@@ -167,9 +183,21 @@ class Workspace:
         return buf
 
 
+def _status_ptr(status, nseq, dev):
+    """Device pointer of an optional per-sequence status tensor (int32 [nseq])."""
+    if status is None:
+        return None
+    if (status.dtype != torch.int32 or tuple(status.shape) != (nseq,) or status.device != dev
+            or not status.is_contiguous()):
+        raise ValueError("status must be a contiguous int32 [%d] tensor on %s" % (nseq, dev))
+    return status.data_ptr()
+
+
 def make_problem(model, y, precision="f32", scan="auto", m_filt=None, P_filt=None,
-                 m_smooth=None, P_smooth=None):
-    """Validate tensors and fill a KfProblem.  Returns (problem, keepalive)."""
+                 m_smooth=None, P_smooth=None, status=None, items=0):
+    """Validate tensors and fill a KfProblem.  Returns (problem, keepalive).
+    ``status`` is an optional int32 [nseq] GPU tensor that receives each
+    sequence's KF_SEQ_* bits (non-finite results are then replaced by NaN)."""
     if precision not in PRECISIONS:
         raise ValueError("precision must be one of %s" % list(PRECISIONS))
     if scan not in SCANS:
@@ -206,7 +234,10 @@ def make_problem(model, y, precision="f32", scan="auto", m_filt=None, P_filt=Non
     p.m_filt, p.P_filt = m_filt.data_ptr(), P_filt.data_ptr()
     if m_smooth is not None:
         p.m_smooth, p.P_smooth = m_smooth.data_ptr(), P_smooth.data_ptr()
-    keep = dict(y=y, m_filt=m_filt, P_filt=P_filt, m_smooth=m_smooth, P_smooth=P_smooth)
+    p.status = _status_ptr(status, nseq, dev)
+    p.items = int(items)
+    keep = dict(y=y, m_filt=m_filt, P_filt=P_filt, m_smooth=m_smooth, P_smooth=P_smooth,
+                status=status)
     return p, keep
 
 
@@ -238,15 +269,16 @@ def _squeeze(x, was2d):
     return x[0] if was2d else x
 
 
-def filter(model, y, precision="f32", scan="auto", workspace=None):  # noqa: A001
+def filter(model, y, precision="f32", scan="auto", workspace=None, status=None,  # noqa: A001
+           items=0):
     """Algorithm 5.  Returns (x_{k|k}, P_{k|k})."""
     was2d = y.dim() == 2
-    p, keep = make_problem(model, y, precision, scan)
+    p, keep = make_problem(model, y, precision, scan, status=status, items=items)
     _call("kf_filter", p, y.device, workspace)
     return _squeeze(keep["m_filt"], was2d), _squeeze(keep["P_filt"], was2d)
 
 
-def _smoother(entry, model, y, precision, scan, workspace):
+def _smoother(entry, model, y, precision, scan, workspace, status=None, items=0):
     was2d = y.dim() == 2
     yy = y.unsqueeze(0) if was2d else y
     nseq, T, _ = yy.shape
@@ -254,22 +286,25 @@ def _smoother(entry, model, y, precision, scan, workspace):
     dt = dtype_for(precision)
     m_s = torch.empty((nseq, T, nx), dtype=dt, device=y.device)
     P_s = torch.empty((nseq, T, nx, nx), dtype=dt, device=y.device)
-    p, keep = make_problem(model, yy, precision, scan, m_smooth=m_s, P_smooth=P_s)
+    p, keep = make_problem(model, yy, precision, scan, m_smooth=m_s, P_smooth=P_s,
+                           status=status, items=items)
     _call(entry, p, y.device, workspace)
     return tuple(_squeeze(keep[k], was2d) for k in ("m_filt", "P_filt", "m_smooth", "P_smooth"))
 
 
-def smooth_rts(model, y, precision="f32", scan="auto", workspace=None):
+def smooth_rts(model, y, precision="f32", scan="auto", workspace=None, status=None, items=0):
     """Algorithm 6.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
-    return _smoother("kf_smooth_rts", model, y, precision, scan, workspace)
+    return _smoother("kf_smooth_rts", model, y, precision, scan, workspace, status, items)
 
 
-def smooth_twofilter(model, y, precision="f32", scan="auto", workspace=None):
+def smooth_twofilter(model, y, precision="f32", scan="auto", workspace=None, status=None,
+                     items=0):
     """Algorithm 7.  Returns (x_{k|k}, P_{k|k}, x_{k|T}, P_{k|T})."""
-    return _smoother("kf_smooth_twofilter", model, y, precision, scan, workspace)
+    return _smoother("kf_smooth_twofilter", model, y, precision, scan, workspace, status, items)
 
 
-def make_batch(models, y, T, offset, precision="f32", scan="auto", smoother=False):
+def make_batch(models, y, T, offset, precision="f32", scan="auto", smoother=False, status=None,
+               items=0, outputs=None):
     """Fill a KfBatch for a ragged batch.  ``models`` holds F, Q, H, R, m0, P0 of
     one shared model, or each with a leading [nseq] dimension (one model per
     sequence); ``y`` is the packed [total_steps, ny] measurements; ``T`` and
@@ -303,13 +338,27 @@ def make_batch(models, y, T, offset, precision="f32", scan="auto", smoother=Fals
             raise ValueError("%s must be a contiguous int64 [nseq] tensor on %s" % (name, dev))
     if y.dtype != dt or not y.is_contiguous():
         raise ValueError("y must be a contiguous %s tensor" % dt)
-    keep = dict(y=y, T=T, offset=offset,
-                m_filt=torch.empty((total, nx), dtype=dt, device=dev),
-                P_filt=torch.empty((total, nx, nx), dtype=dt, device=dev),
-                m_smooth=None, P_smooth=None)
-    if smoother:
-        keep["m_smooth"] = torch.empty((total, nx), dtype=dt, device=dev)
-        keep["P_smooth"] = torch.empty((total, nx, nx), dtype=dt, device=dev)
+    if outputs is not None:
+        # caller-owned output arrays (m_filt, P_filt[, m_smooth, P_smooth]) of
+        # [total_steps, nx] / [total_steps, nx, nx]
+        outs = list(outputs) + [None] * (4 - len(outputs))
+        for t, shp in zip(outs, [(total, nx), (total, nx, nx)] * 2):
+            if t is not None and (tuple(t.shape) != shp or t.dtype != dt or t.device != dev
+                                  or not t.is_contiguous()):
+                raise ValueError("output arrays must be contiguous %s tensors of shape %s"
+                                 % (dt, shp))
+        keep = dict(y=y, T=T, offset=offset, m_filt=outs[0], P_filt=outs[1],
+                    m_smooth=outs[2], P_smooth=outs[3])
+        if smoother and outs[2] is None:
+            raise ValueError("a smoother needs m_smooth and P_smooth outputs")
+    else:
+        keep = dict(y=y, T=T, offset=offset,
+                    m_filt=torch.empty((total, nx), dtype=dt, device=dev),
+                    P_filt=torch.empty((total, nx, nx), dtype=dt, device=dev),
+                    m_smooth=None, P_smooth=None)
+        if smoother:
+            keep["m_smooth"] = torch.empty((total, nx), dtype=dt, device=dev)
+            keep["P_smooth"] = torch.empty((total, nx, nx), dtype=dt, device=dev)
     b = KfBatch()
     b.nx, b.ny, b.precision, b.scan = nx, ny, PRECISIONS[precision], SCANS[scan]
     b.nseq, b.nmodels, b.total_steps = nseq, nmodels, total
@@ -319,6 +368,9 @@ def make_batch(models, y, T, offset, precision="f32", scan="auto", smoother=Fals
     b.m_filt, b.P_filt = keep["m_filt"].data_ptr(), keep["P_filt"].data_ptr()
     if smoother:
         b.m_smooth, b.P_smooth = keep["m_smooth"].data_ptr(), keep["P_smooth"].data_ptr()
+    b.status = _status_ptr(status, nseq, dev)
+    b.items = int(items)
+    keep["status"] = status
     return b, keep
 
 
@@ -331,11 +383,15 @@ def batch_workspace_size(b: KfBatch) -> int:
 
 def workspace_status(ws: torch.Tensor) -> int:
     """Error bits of the last call on this workspace (synchronises the current
-    stream): 1 = a look-back wait gave up, 2 = invalid ragged-batch entries."""
+    stream): KF_WS_TIMEOUT = a look-back wait gave up, KF_WS_INVALID = invalid
+    ragged-batch entries, KF_WS_NUMERIC = a sequence's outputs held non-finite
+    values (calls with a status tensor only)."""
     flag = ctypes.c_uint32(0)
     stream = torch.cuda.current_stream(ws.device).cuda_stream
-    _check(load_library().kf_workspace_status(ws.data_ptr(), ws.numel() * ws.element_size(),
-                                              ctypes.byref(flag), stream), "kf_workspace_status")
+    rc = load_library().kf_workspace_status(ws.data_ptr(), ws.numel() * ws.element_size(),
+                                            ctypes.byref(flag), stream)
+    if rc != KF_ERR_NUMERIC:
+        _check(rc, "kf_workspace_status")
     return flag.value
 
 
@@ -354,12 +410,14 @@ def run_batch(entry, b: KfBatch, device, workspace=None):
     return ws
 
 
-def batch(entry, models, y, T, offset, precision="f32", scan="auto", workspace=None):
+def batch(entry, models, y, T, offset, precision="f32", scan="auto", workspace=None,
+          status=None, items=0):
     """One ragged-batch call; entry is "filter", "rts" or "tf".  Returns the
     packed outputs (m_filt, P_filt[, m_smooth, P_smooth]) and the workspace."""
     name = {"filter": "kf_filter_batch", "rts": "kf_smooth_rts_batch",
             "tf": "kf_smooth_twofilter_batch"}[entry]
-    b, keep = make_batch(models, y, T, offset, precision, scan, smoother=(entry != "filter"))
+    b, keep = make_batch(models, y, T, offset, precision, scan, smoother=(entry != "filter"),
+                         status=status, items=items)
     ws = run_batch(name, b, y.device, workspace)
     outs = (keep["m_filt"], keep["P_filt"])
     if entry != "filter":
@@ -367,7 +425,8 @@ def batch(entry, models, y, T, offset, precision="f32", scan="auto", workspace=N
     return outs, ws
 
 
-def tv(entry, F, Q, H, R, u, d, m0, P0, y, precision="f32", scan="auto", workspace=None):
+def tv(entry, F, Q, H, R, u, d, m0, P0, y, precision="f32", scan="auto", workspace=None,
+       status=None):
     """A time-varying model (kf_*_tv): F, Q [T, nx, nx], H [T, ny, nx], R [T, ny, ny],
     u [T, nx] or None, d [T, ny] or None (row j belongs to step j+1), prior m0,
     P0, measurements y [T, ny] or [nseq, T, ny].  entry is "filter", "rts" or
@@ -410,6 +469,7 @@ def tv(entry, F, Q, H, R, u, d, m0, P0, y, precision="f32", scan="auto", workspa
     p.m_filt, p.P_filt = outs[0].data_ptr(), outs[1].data_ptr()
     if entry != "filter":
         p.m_smooth, p.P_smooth = outs[2].data_ptr(), outs[3].data_ptr()
+    p.status = _status_ptr(status, nseq, dev)
     lib = load_library()
     n = ctypes.c_size_t(0)
     _check(lib.kf_tv_workspace_size(ctypes.byref(p), ctypes.byref(n)), "kf_tv_workspace_size")
@@ -428,7 +488,8 @@ class Plan:
     for stage-by-stage launches (kf_prepare, kf_pass_*), e.g. to time each
     kernel with events on the current stream."""
 
-    def __init__(self, model, y, precision="f32", scan="auto", smoother=True, workspace=None):
+    def __init__(self, model, y, precision="f32", scan="auto", smoother=True, workspace=None,
+                 items=0):
         was2d = y.dim() == 2
         yy = y.unsqueeze(0) if was2d else y
         nseq, T, _ = yy.shape
@@ -440,7 +501,7 @@ class Plan:
             self.m_s = torch.empty((nseq, T, nx), dtype=dt, device=y.device)
             self.P_s = torch.empty((nseq, T, nx, nx), dtype=dt, device=y.device)
         self.p, self.keep = make_problem(model, yy, precision, scan, m_smooth=self.m_s,
-                                         P_smooth=self.P_s)
+                                         P_smooth=self.P_s, items=items)
         self.device = y.device
         self.need = workspace_size(self.p)
         self.ws = workspace if workspace is not None else torch.empty(
@@ -476,6 +537,42 @@ def scan_counts(scan: str, T: int) -> tuple[int, int]:
     _check(load_library().kf_scan_counts(SCANS[scan], T, ctypes.byref(c), ctypes.byref(n)),
            "kf_scan_counts")
     return c.value, n.value
+
+
+AFFINE_MODULUS = {"f64": 33554393, "f32": 2039}
+
+
+def selftest_scan(elems: torch.Tensor, reverse: bool = False, items: int = 8,
+                  group: int = 1) -> torch.Tensor:
+    """Run a look-back scan skeleton with the exact affine operator of
+    kf_selftest_scan over ``elems`` [nseq, T, 10] (float64 or float32 integers
+    below AFFINE_MODULUS); returns the composed maps' (b, C) [nseq, T, 6].
+    group 1 is the thread driver, 8 or 16 the group driver of the wide scans."""
+    if elems.dim() != 3 or elems.shape[-1] != 10 or not elems.is_contiguous():
+        raise ValueError("elems must be a contiguous [nseq, T, 10] tensor")
+    if elems.device.type != "cuda":
+        raise KfScanError("kfscan runs on the GPU only; elems is on %s" % elems.device)
+    prec = {torch.float64: 0, torch.float32: 1}.get(elems.dtype)
+    if prec is None:
+        raise ValueError("elems must be float64 or float32")
+    nseq, T, _ = elems.shape
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.kf_selftest_scan_workspace(prec, group, items, T, nseq, ctypes.byref(n)),
+           "kf_selftest_scan_workspace")
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=elems.device)
+    out = torch.empty((nseq, T, 6), dtype=elems.dtype, device=elems.device)
+    stream = torch.cuda.current_stream(elems.device).cuda_stream
+    _check(lib.kf_selftest_scan(prec, group, int(bool(reverse)), items, T, nseq,
+                                elems.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                stream), "kf_selftest_scan")
+    if CHECK:
+        flag = ctypes.c_uint32(0)
+        rc = lib.kf_workspace_status(ws.data_ptr(), ws.numel(), ctypes.byref(flag), stream)
+        _check(rc, "kf_workspace_status")
+        if flag.value & KF_WS_TIMEOUT:
+            raise KfScanError("kf_selftest_scan: a look-back wait timed out")
+    return out
 
 
 def supported(nx: int, ny: int, precision: str = "f32") -> bool:

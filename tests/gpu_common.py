@@ -30,6 +30,44 @@ def normwise(a, ref) -> float:
     return float(np.max(np.abs(a - ref)) / scale)
 
 
+# Per-component bounds (FP64 only): every state component of a mean, and every
+# covariance entry, against its own scale (componentwise), and the error of
+# the means in posterior standard deviations (zscore).
+TOL_COMPONENT = {"f64": 1e-9}
+TOL_Z = {"f64": 1e-6}
+
+
+def componentwise(a, ref) -> float:
+    """Largest error of one state component or covariance entry, each scaled by
+    its own size: a mean's component i by max_k |ref[k, i]|, a covariance
+    entry (i, j) by sqrt(max_k ref[k, i, i] * max_k ref[k, j, j]).  Unlike
+    normwise, large components (positions of about 1e7 on long tracks) do
+    not hide the errors of small ones (velocities)."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    err = np.abs(a - ref)
+    lead = tuple(range(ref.ndim - (2 if ref.ndim >= 3 else 1)))
+    if ref.ndim >= 3 and ref.shape[-1] == ref.shape[-2]:
+        d = np.max(np.abs(np.diagonal(ref, axis1=-2, axis2=-1)), axis=lead)
+        scale = np.sqrt(np.outer(d, d))
+        e = np.max(err, axis=lead)
+    else:
+        scale = np.max(np.abs(ref), axis=lead)
+        e = np.max(err, axis=lead)
+    glob = np.max(np.abs(ref)) if ref.size else 1.0
+    scale = np.where(scale > 0, scale, glob if glob > 0 else 1.0)
+    return float(np.max(e / scale)) if e.size else 0.0
+
+
+def zscore(m, m_ref, P_ref) -> float:
+    """max_{k,i} |m - m_ref| / sqrt(P_ref[k, i, i]): the error of the means in
+    posterior standard deviations."""
+    m = np.asarray(m, dtype=np.float64)
+    m_ref = np.asarray(m_ref, dtype=np.float64)
+    sd = np.sqrt(np.diagonal(np.asarray(P_ref, dtype=np.float64), axis1=-2, axis2=-1))
+    return float(np.max(np.abs(m - m_ref) / sd)) if m.size else 0.0
+
+
 def to_dev(model, precision):
     k = kfscan()
     return k.model_to_device(model.arrays(), precision)

@@ -42,8 +42,8 @@ def test_every_declared_symbol_is_exported(kfscan):
 
 def test_abi_version_and_status_strings(kfscan):
     lib = kfscan.load_library()
-    assert lib.kf_abi_version() == 4
-    for code in range(5):
+    assert lib.kf_abi_version() == 5
+    for code in range(6):
         assert kfscan.status_string(code)
 
 

@@ -16,7 +16,8 @@ import pytest
 
 import oracle
 import kf_workloads as W
-from tests.gpu_common import TOL, gpu_available, kfscan, normwise, oracle_inputs_for, torch
+from tests.gpu_common import (TOL, TOL_COMPONENT, TOL_Z, componentwise, gpu_available, kfscan,
+                              normwise, oracle_inputs_for, zscore, torch)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -51,7 +52,12 @@ def _compare(entry, model, y, prec, scan="auto"):
     else:
         ref = list(oracle.smooth_twofilter(*arrs, yy))
     errs = [normwise(g, r) for g, r in zip(got, ref)]
-    _say(entry, prec, scan, "T=%d" % len(y), "errors", errs)
+    comp = [componentwise(g, r) for g, r in zip(got, ref)]
+    zs = [zscore(got[i], ref[i], ref[i + 1]) for i in range(0, len(got), 2)]
+    _say(entry, prec, scan, "T=%d" % len(y), "errors", errs, "componentwise", comp, "z", zs)
+    if prec == "f64":
+        assert max(comp) <= TOL_COMPONENT["f64"], comp
+        assert max(zs) <= TOL_Z["f64"], zs
     return errs
 
 

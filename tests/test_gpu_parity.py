@@ -7,8 +7,8 @@ import pytest
 
 import oracle
 import kf_workloads as W
-from tests.gpu_common import (TOL, gpu_available, kfscan, normwise, oracle_inputs_for, to_dev,
-                              y_dev, torch)
+from tests.gpu_common import (TOL, TOL_COMPONENT, TOL_Z, componentwise, gpu_available, kfscan,
+                              normwise, oracle_inputs_for, to_dev, y_dev, zscore, torch)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -54,6 +54,15 @@ def _check(entry, model, y, prec, tol=None, scan="auto"):
         errs[name] = normwise(g, r)
     for name, e in errs.items():
         assert e <= tol, (entry, prec, name, errs)
+    # FP64: every component and covariance entry on its own scale, and the
+    # means to a small fraction of a posterior standard deviation
+    if prec == "f64" and tol == TOL["f64"]:
+        for name, g, r in zip(names, got, ref):
+            c = componentwise(g, r)
+            assert c <= TOL_COMPONENT["f64"], (entry, name, "componentwise", c)
+        for i in range(0, len(got), 2):
+            z = zscore(got[i], ref[i], ref[i + 1])
+            assert z <= TOL_Z["f64"], (entry, names[i], "zscore", z)
     # covariances are exactly symmetric
     for g in got[1::2]:
         assert np.array_equal(g, np.swapaxes(g, -1, -2))
