@@ -324,6 +324,24 @@ kf_status kf_pass_rts(const kf_problem *p, void *workspace, size_t workspace_byt
 kf_status kf_pass_twofilter(const kf_problem *p, void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* ---- An entry point that allocates nothing ------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * kf_smooth_rts_noalloc is kf_smooth_rts (Algorithm 6, same kernels, same
+ * results) with its workspace in a static device array of
+ * KF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; it calls no allocating routine.  The caller still
+ * passes every input and output array.  A problem whose kf_workspace_size
+ * exceeds KF_NOALLOC_SCRATCH_BYTES is refused with KF_ERR_WORKSPACE before
+ * anything is enqueued (16 MiB covers the nx = 4 tracking workload up to about
+ * T = 2^25 in FP32).  The array is shared by every call on a GPU and keeps the
+ * last call's contents (the call re-initialises what it needs): calls that
+ * may overlap on one GPU (other streams, other host threads) race and must
+ * use kf_smooth_rts with their own workspaces.  `stream` must belong to the
+ * current device. */
+#define KF_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+kf_status kf_smooth_rts_noalloc(const kf_problem *p, void *stream);
+
 /* ---- Self-test of the scan skeleton ------------------------------------
  * The single-pass look-back drivers of the scans above (fold, wavefront scan,
  * windowed decoupled look-back with anchors, step walk): group = 1 runs the
