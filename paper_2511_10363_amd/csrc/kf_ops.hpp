@@ -399,6 +399,29 @@ KF_DEV void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Determinant of a K x K matrix (K <= 3) by cofactor expansion.
+template <int K, class T> KF_DEV T det_small(const T (&a)[3][3]) {
+  if constexpr (K == 0) return T(1);
+  else if constexpr (K == 1) return a[0][0];
+  else if constexpr (K == 2) return a[0][0] * a[1][1] - a[0][1] * a[1][0];
+  else
+    return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+           a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+           a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+}
+
+// Cofactor (r, c) of the N x N matrix M (N <= 4): the signed determinant of
+// M without row r and column c (rows and columns picked by index, from LDS).
+template <int N, class T> KF_DEV T cofactor(const T (&M)[N][N], int r, int c) {
+  T a[3][3];
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i)
+#pragma unroll
+    for (int j = 0; j < N - 1; ++j) a[i][j] = M[i + (i >= r)][j + (j >= c)];
+  const T d = det_small<N - 1, T>(a);
+  return ((r + c) & 1) ? -d : d;
+}
+
 // Coefficients of the vector part of Lemma 1 for left x (matrix part Sx) and
 // right y (matrix part Sy): with M = I + C_x J_y and Z = M^{-1} A_x,
 //   b = P1 b_x + P2 eta_y + b_y,   eta = P3 eta_y - P4 b_x + eta_x,
@@ -408,14 +431,18 @@ KF_DEV void wave_lds_sync() {
 // l = r*N + c owning entry (r, c) of every result; every lane of the
 // wavefront must call it (it synchronises the wavefront between phases).
 // x, y, o, the coefficients Pc = {P1, P2, P3, P4} and the scratch W live in
-// LDS; o must not alias x or y.  Each lane factorises M = I + C_x J_y itself
-// and solves for column c of Z = M^{-1} A_x and Y = M^{-1} C_x and for row r
-// of P1 = A_y M^{-1}; the products then take one dot product per lane.
-// Symmetric results are formed from the upper triangle in both lanes (r, c)
-// and (c, r), so they are exactly symmetric.
+// LDS; o must not alias x or y.  M^{-1} is formed from cofactors: lane
+// (r, c) forms the cofactor of entry (r, c), every lane the determinant from
+// the cofactors of row 0, so the inverse takes a few dependent operations
+// per lane instead of a whole pivoted factorisation.  (M has eigenvalues
+// >= 1, since C_x and J_y are positive semi-definite, so its determinant is
+// >= 1.)  The products then take one dot product per lane.  Symmetric results
+// are formed from the upper triangle in both lanes (r, c) and (c, r), so they
+// are exactly symmetric.
 template <int N, class T>
 KF_DEV void mpart_combine_lanes(const MPart<N, T>& x, const MPart<N, T>& y, MPart<N, T>& o,
                                 T (&Pc)[4][N][N], T (&W)[4][N][N], int lane) {
+  static_assert(N <= 4, "cofactor inverse of at most 4 x 4");
   const bool on = lane < N * N;
   const int r = on ? lane / N : 0, c = on ? lane % N : 0;
   const int i = r < c ? r : c, j = r < c ? c : r;
@@ -426,27 +453,25 @@ KF_DEV void mpart_combine_lanes(const MPart<N, T>& x, const MPart<N, T>& y, MPar
     W[0][r][c] = m;
   }
   wave_lds_sync();
+  if (on) W[3][r][c] = cofactor<N, T>(W[0], r, c);
+  wave_lds_sync();
+  T idet = T(0);
   if (on) {
-    T M[N][N], dinv[N], zc[N][1], yc[N][1], p1[N];
-    int piv[N];
+    T det = T(0);
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
+    for (int t = 0; t < N; ++t) det += W[0][0][t] * W[3][0][t];
+    idet = krcp(det);
+  }
+  wave_lds_sync();
+  if (on) W[0][c][r] = W[3][r][c] * idet;  // M^{-1} = adj(M) / det(M)
+  wave_lds_sync();
+  if (on) {
+    T zr = T(0), yr = T(0), pr = T(0);
 #pragma unroll
-      for (int b = 0; b < N; ++b) M[a][b] = W[0][a][b];
-      zc[a][0] = x.A[a][c];
-      yc[a][0] = x.C[a][c];
-      p1[a] = y.A[r][a];
-    }
-    lu_factor<N, T>(M, piv, dinv);
-    lu_solve<N, 1, T>(M, piv, dinv, zc);
-    lu_solve<N, 1, T>(M, piv, dinv, yc);
-    lu_solve_t<N, T>(M, piv, dinv, p1);
-    T zr = zc[0][0], yr = yc[0][0], pr = p1[0];
-#pragma unroll
-    for (int a = 1; a < N; ++a) {
-      zr = (a == r) ? zc[a][0] : zr;
-      yr = (a == r) ? yc[a][0] : yr;
-      pr = (a == c) ? p1[a] : pr;
+    for (int t = 0; t < N; ++t) {
+      zr += W[0][r][t] * x.A[t][c];
+      yr += W[0][r][t] * x.C[t][c];
+      pr += y.A[r][t] * W[0][t][c];
     }
     W[1][r][c] = zr;  // Z
     W[2][r][c] = yr;  // Y

@@ -32,11 +32,16 @@ inline long ntiles_for(long T, int items) {
 
 // States wider than nx = 4 are scanned by groups of nx lanes (kf_wide.hpp):
 // workgroups of wide_block(nx) threads, each group owning wide_items(nx)
-// steps, so a tile holds wide_block(nx) / nx * wide_items(nx) steps.  256
-// threads at nx = 8 (32 groups), 128 at nx = 16 (8 groups), whose LDS
-// scratch and look-back buffers then leave room for several workgroups per CU.
+// steps, so a tile holds wide_block(nx) / nx * wide_items(nx) steps: 256
+// threads at nx = 8 (32 groups, 512-step tiles) and a single wavefront at
+// nx = 16 (4 groups, 64-step tiles).  The nx = 16 kernels spill registers to
+// per-lane scratch memory, and a workgroup of several wavefronts can then be
+// started wavefront by wavefront as scratch frees up: a tile whose
+// workgroup is only partly running would hold up every later tile waiting
+// for it, while those waiting workgroups hold the scratch it needs.  A
+// one-wavefront workgroup is running in full as soon as it takes its tile.
 inline bool is_wide(int nx) { return nx > 4; }
-constexpr int wide_block(int nx) { return nx <= 8 ? 256 : 128; }
+constexpr int wide_block(int nx) { return nx <= 8 ? 256 : 64; }
 constexpr int wide_items(int) { return 16; }
 inline long wide_tile(int nx) { return (long)(wide_block(nx) / nx) * wide_items(nx); }
 

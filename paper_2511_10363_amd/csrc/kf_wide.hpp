@@ -906,8 +906,10 @@ KF_DEV void gscan_tile(Pipe& pp, const ScanArgs<R>& a) {
       tag_load<R>(sp, a.pre + ((base + idx) * N + r) * PSW, tag, a.ctr + 2);
       pp.expand(sp, v);
     };
+    // tiles per group in a look-back window: one window reaches back over a
+    // sequence of up to 16 * NG tiles
     const long gq = (si.ntiles + NG - 1) / NG;
-    const int Gw = (int)(gq < 1 ? 1 : (gq > 8 ? 8 : gq));
+    const int Gw = (int)(gq < 1 ? 1 : (gq > 16 ? 16 : gq));
     E ex = glookback<BLOCK, G, E>(a.flags + base, a.ctr + 2, tag, t, Gw, op, load_agg, expand,
                                   s_part, s_lp, &s_f1);
     if (grp == 0) {

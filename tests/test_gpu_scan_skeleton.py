@@ -73,8 +73,8 @@ def test_scan_skeleton_many_tiles(reverse):
 
 # ---------------------------------------------------------------------------
 # The group driver of the wide-state scans (groups of 8 lanes in 256-thread
-# workgroups, 16 lanes in 128-thread ones): tiles of 32 x items and 8 x items
-# steps, look-back windows of 256 and 64 tiles.
+# workgroups, 16 lanes in one-wavefront ones): tiles of 32 x items and
+# 4 x items steps, look-back windows of 32 x 16 and 4 x 16 tiles.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("reverse", [False, True])
@@ -93,8 +93,8 @@ def test_group_skeleton_exact(prec, reverse, group, items, T):
 @pytest.mark.parametrize("reverse", [False, True])
 @pytest.mark.parametrize("group", [8, 16])
 def test_group_skeleton_many_windows(reverse, group):
-    """100003 steps in tiles of 16 (G = 16) or 64 (G = 8) steps: 6251 or 1563
-    tiles, against windows of 64 or 256 tiles, so a tile that finds no
+    """100003 steps in tiles of 8 (G = 16) or 64 (G = 8) steps: 12501 or 1563
+    tiles, against windows of 64 or 512 tiles, so a tile that finds no
     published prefix nearby folds several windows."""
     p = kfscan().AFFINE_MODULUS["f64"]
     rng = np.random.default_rng(group)

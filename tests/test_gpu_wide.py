@@ -1,7 +1,7 @@
 """GPU parity of the wide-state scans (nx = 8, ny = 4 and nx = 16, ny = 8):
 elements spread over groups of nx lanes (kf_wide.hpp), for the filter (Lemma
 1), the RTS smoother (Lemma 2) and the two-filter smoother, against the CPU
-FP64 oracle, at lengths around the tile sizes (512 steps at nx = 8, 128 at
+FP64 oracle, at lengths around the tile sizes (512 steps at nx = 8, 64 at
 nx = 16) and inside ragged batches with a model per sequence."""
 import sys
 
@@ -111,19 +111,12 @@ def test_wide_batch(nx, ny, entry, prec):
             assert normwise(g[a:b], rr) <= TOL[prec], (i, lengths[i], normwise(g[a:b], rr))
 
 
-MULTI_WINDOW = pytest.mark.skip(
-    reason="more tiles than one look-back window of the group scan (64 tiles at nx = 16): a "
-           "look-back wait gave up on the first such case (nx = 16, mixed, T = 20000); kept "
-           "off the GPU until its cause is found (the design notes record it)")
-
-
-@pytest.mark.parametrize("nx,ny,T,prec", [
-    (8, 4, 1 << 16, "f32"),
-    pytest.param(16, 8, 20000, "mixed", marks=MULTI_WINDOW),
-    pytest.param(16, 8, 9000, "f64", marks=MULTI_WINDOW)])
+@pytest.mark.parametrize("nx,ny,T,prec", [(8, 4, 1 << 16, "f32"), (16, 8, 20000, "mixed"),
+                                          (16, 8, 9000, "f64"), (16, 8, 65536, "f32")])
 def test_wide_long(nx, ny, T, prec):
     """Many tiles per sequence (RTS, which runs the filter first): 128 tiles of
-    512 steps at nx = 8, one look-back window of 32 groups x 4 tiles."""
+    512 steps at nx = 8 (one look-back window of 32 groups x 4 tiles); 141 to
+    1024 tiles of 64 steps at nx = 16, over windows of 4 groups x 16 tiles."""
     k = kfscan()
     model, rng = _model(nx, ny, 5)
     y = W.simulate(model, T, rng)
