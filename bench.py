@@ -96,6 +96,9 @@ def main() -> int:
                          "sequential filter on one GPU lane, over a range of T; scans: "
                          "every scan algorithm with each of the three pipelines")
     ap.add_argument("--jobs", type=int, default=2000, help="jobs of the serving workload")
+    ap.add_argument("--no-extra-configs", dest="extra_configs", action="store_false",
+                    help="skip the T = 1000 FP64 and T = 2^18 two-filter lines after the "
+                         "headline")
     ap.add_argument("--nx", type=int, default=16, help="state size of the serving workload")
     ap.add_argument("--arena-rows", type=int, default=1 << 22,
                     help="rows of the serving arena (admission capacity)")
@@ -288,8 +291,64 @@ def main() -> int:
         "graph_ms_per_step": graph_ms,
         "errors_vs_oracle": errors,
     }
+    if args.extra_configs and args.T <= 0 and args.log2T == 20:
+        out["other_configs"] = other_configs(args, np, torch, W, kfscan, dev)
     print(json.dumps(out))
     return 0
+
+
+def other_configs(args, np, torch, W, kfscan, dev) -> dict:
+    """The two other single-sequence configurations of the tracking model, run
+    after the headline: T = 1000 in FP64 (filter + RTS), and T = 2^18 with the
+    two-filter smoother in FP32 storage with FP64 solves.  Each: event-timed
+    passes (prepare + forward + backward, median of 50 after 5 warm-up) and,
+    with the CPU-baseline leg on, the errors against the FP64 sequential RTS
+    smoother of the oracle."""
+    import oracle
+
+    res = {}
+    for name, T, prec, back, oracle_fn in (
+            ("T1000_f64_filter_rts", 1000, "f64", "kf_pass_rts", oracle.smooth_rts),
+            ("T2^18_mixed_filter_twofilter", 1 << 18, "mixed", "kf_pass_twofilter",
+             oracle.smooth_rts)):
+        model, y_np = W.tracking(T, seed=args.seed)
+        dt = kfscan.dtype_for(prec)
+        dmodel = kfscan.model_to_device(model.arrays(), prec, dev)
+        y = torch.as_tensor(y_np).to(dev, dt).contiguous()
+        plan = kfscan.Plan(dmodel, y, precision=prec, smoother=True)
+
+        def one():
+            plan("kf_prepare")
+            plan("kf_pass_filter")
+            plan(back)
+        for _ in range(5):
+            one()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(50):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            one()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        res[name] = {"ms_per_pass": ms, "steps_per_s": T / (ms * 1e-3),
+                     "errors_vs_fp64_rts_oracle": None}
+        if args.cpu_seconds <= 0:
+            continue
+        arrs, yy = model.arrays(), y_np
+        if prec != "f64":
+            cast = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+            arrs, yy = tuple(cast(a) for a in arrs), cast(y_np)
+        ref = oracle_fn(*arrs, yy)
+        got = [t[0].double().cpu().numpy() for t in plan.outputs()]
+        errs = {k: float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300))
+                for k, g, r in zip(("m_filt", "P_filt", "m_smooth", "P_smooth"), got, ref)}
+        errs["z_smooth_max"] = float(np.max(np.abs(got[2] - ref[2]) /
+                                            np.sqrt(np.einsum("kii->ki", ref[3]))))
+        res[name]["errors_vs_fp64_rts_oracle"] = errs
+    return res
 
 
 def bench_batched(args, np, torch, W, kfscan, dev) -> int:

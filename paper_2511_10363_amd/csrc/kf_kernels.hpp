@@ -17,6 +17,7 @@
 // counters are zeroed by the preparation kernel that precedes the scans.
 #pragma once
 #include <cstdint>
+#include <type_traits>
 
 #include "kf_scan.hpp"
 
@@ -95,134 +96,192 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   __shared__ D sW[4][N][N];           // combine scratch
   __shared__ D sPHI[2][LMAX][N][M], sPSI[2][LMAX][N][M];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-  auto load_model = [&](D (&F)[N][N], D (&Q)[N][N], D (&H)[M][N], D (&Rm)[M][M]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        F[i][j] = D(F_[i * N + j]);
-        Q[i][j] = D(Q_[i * N + j]);
-      }
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) H[i][j] = D(H_[i * N + j]);
-#pragma unroll
-      for (int j = 0; j < M; ++j) Rm[i][j] = D(R_[i * M + j]);
+  // The two elements are derived entry-parallel in FP64, one wavefront each
+  // (lane r*cols + c owns entry (r, c) of each product, the wavefront
+  // synchronising between products), with the same operations per entry as
+  // the sequential formulas; symmetric results are formed from the upper
+  // triangle in both lanes (r, c) and (c, r).
+  __shared__ D mF[2][N][N], mQ[2][N][N], mH[2][M][N], mR[2][M][M];
+  const int l = lane;
+  const int wv = tid / WAVE;
+  if (wv < 2) {
+    if (l < N * N) {
+      mF[wv][l / N][l % N] = D(F_[l]);
+      mQ[wv][l / N][l % N] = D(Q_[l]);
     }
-  };
-  if (tid == 0) {
+    if (l < M * N) mH[wv][l / N][l % N] = D(H_[l]);
+    if (l < M * M) mR[wv][l / M][l % M] = D(R_[l]);
+    wave_lds_sync();
+  }
+  if (wv == 0) {
     // generic element (eq. pkf_init1)
-    D F[N][N], Q[N][N], H[M][N], Rm[M][M];
-    load_model(F, Q, H, Rm);
-    D HQ[M][N], S[M][M], sd[M];
-    mm<M, N, N, D>(H, Q, HQ);
-    sym_xyt_plus<M, N, D>(HQ, H, Rm, S);
-    chol_factor<M, D>(S, sd);
-    D Kt[M][N];  // K^T = S^{-1} H Q
-    copy_mat<M, N, D>(HQ, Kt);
-    chol_solve<M, N, D>(S, sd, Kt);
-    D IKH[N][N];
+    const D(&F)[N][N] = mF[0];
+    const D(&Q)[N][N] = mQ[0];
+    const D(&H)[M][N] = mH[0];
+    const D(&Rm)[M][M] = mR[0];
+    __shared__ D gHQ[M][N], gHF[M][N], gS[M][M], gKt[M][N], gWt[M][N], gIKH[N][N];
+    if (l < M * N) {
+      const int i = l / N, j = l % N;
+      D hq = D(0), hf = D(0);
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        D s = (i == j) ? D(1) : D(0);
-#pragma unroll
-        for (int t = 0; t < M; ++t) s -= Kt[t][i] * H[t][j];
-        IKH[i][j] = s;
+      for (int t = 0; t < N; ++t) {
+        hq += H[i][t] * Q[t][j];
+        hf += H[i][t] * F[t][j];
       }
-    D A[N][N], C[N][N];
-    mm<N, N, N, D>(IKH, F, A);
-    mm<N, N, N, D>(IKH, Q, C);
-    D HF[M][N], Wt[M][N];  // W^T = S^{-1} H F
-    mm<M, N, N, D>(H, F, HF);
-    copy_mat<M, N, D>(HF, Wt);
-    chol_solve<M, N, D>(S, sd, Wt);
-    D Jm[N][N], Z[N][N];
+      gHQ[i][j] = hq;
+      gHF[i][j] = hf;
+    }
+    wave_lds_sync();
+    if (l < M * M) {  // S = H Q H^T + R
+      const int i = l / M, j = l % M, a = i < j ? i : j, b = i < j ? j : i;
+      D sv = Rm[a][b];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+      for (int t = 0; t < N; ++t) sv += gHQ[a][t] * H[b][t];
+      gS[i][j] = sv;
+    }
+    wave_lds_sync();
+    if (l < N) {  // column l of K^T = S^{-1} H Q and of W^T = S^{-1} H F
+      D Sr[M][M], sd[M], B[M][2];
 #pragma unroll
-      for (int j = 0; j < N; ++j) Z[i][j] = D(0);
-    sym_xty_plus<N, M, D>(Wt, HF, Z, Jm);  // J = (S^{-1} H F)^T (H F)
+      for (int i = 0; i < M; ++i) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const D Cs = 0.5 * (C[i][j] + C[j][i]);
-        cst[LY::A + i * N + j] = R(A[i][j]);
-        cst[LY::C + i * N + j] = R(Cs);
-        cst[LY::J + i * N + j] = R(Jm[i][j]);
-        sS[0].A[i][j] = A[i][j];
-        sS[0].C[i][j] = Cs;
-        sS[0].J[i][j] = Jm[i][j];
+        for (int j = 0; j < M; ++j) Sr[i][j] = gS[i][j];
+        B[i][0] = gHQ[i][l];
+        B[i][1] = gHF[i][l];
       }
+      chol_factor<M, D>(Sr, sd);
+      chol_solve<M, 2, D>(Sr, sd, B);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        gKt[i][l] = B[i][0];
+        gWt[i][l] = B[i][1];
+      }
+    }
+    wave_lds_sync();
+    D Jv = D(0);
+    if (l < N * N) {  // I - K H, and J = (S^{-1} H F)^T (H F)
+      const int i = l / N, j = l % N, a = i < j ? i : j, b = i < j ? j : i;
+      D v = (i == j) ? D(1) : D(0);
 #pragma unroll
       for (int t = 0; t < M; ++t) {
-        cst[LY::K + i * M + t] = R(Kt[t][i]);
-        cst[LY::W + i * M + t] = R(Wt[t][i]);
-        sPHI[0][0][i][t] = Kt[t][i];
-        sPSI[0][0][i][t] = Wt[t][i];
+        v -= gKt[t][i] * H[t][j];
+        Jv += gWt[t][a] * gHF[t][b];
       }
+      gIKH[i][j] = v;
     }
-  } else if (tid == WAVE) {
+    wave_lds_sync();
+    if (l < N * N) {  // A = (I - K H) F, C = (I - K H) Q symmetrised
+      const int i = l / N, j = l % N;
+      D av = D(0), c1 = D(0), c2 = D(0);
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        av += gIKH[i][t] * F[t][j];
+        c1 += gIKH[i][t] * Q[t][j];
+        c2 += gIKH[j][t] * Q[t][i];
+      }
+      const D Cs = 0.5 * (c1 + c2);
+      cst[LY::A + i * N + j] = R(av);
+      cst[LY::C + i * N + j] = R(Cs);
+      cst[LY::J + i * N + j] = R(Jv);
+      sS[0].A[i][j] = av;
+      sS[0].C[i][j] = Cs;
+      sS[0].J[i][j] = Jv;
+    }
+    if (l < N * M) {
+      const int i = l / M, t = l % M;
+      cst[LY::K + i * M + t] = R(gKt[t][i]);
+      cst[LY::W + i * M + t] = R(gWt[t][i]);
+      sPHI[0][0][i][t] = gKt[t][i];
+      sPSI[0][0][i][t] = gWt[t][i];
+    }
+  } else if (wv == 1) {
     // first element (eq. pkf_init2) and the model copies
-    D F[N][N], Q[N][N], H[M][N], Rm[M][M], m0[N], P0[N][N];
-    load_model(F, Q, H, Rm);
+    const D(&F)[N][N] = mF[1];
+    const D(&Q)[N][N] = mQ[1];
+    const D(&H)[M][N] = mH[1];
+    const D(&Rm)[M][M] = mR[1];
+    __shared__ D fP0[N][N], fm0[N], fx[N], fFP[N][N], fP[N][N], fHP[M][N], fHx[M], fS[M][M],
+        fK[M][N];
+    if (l < N * N) fP0[l / N][l % N] = D(P0_[l]);
+    if (l < N) fm0[l] = D(m0_[l]);
+    wave_lds_sync();
+    if (l < N * N) {  // copies: F, Q and P0 symmetrised, m0
+      const int i = l / N, j = l % N;
+      cst[LY::F + l] = R(F[i][j]);
+      cst[LY::Q + l] = R(0.5 * (Q[i][j] + Q[j][i]));
+      cst[LY::P0 + l] = R(0.5 * (fP0[i][j] + fP0[j][i]));
+      D fp = D(0);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      m0[i] = D(m0_[i]);
-#pragma unroll
-      for (int j = 0; j < N; ++j) P0[i][j] = D(P0_[i * N + j]);
+      for (int t = 0; t < N; ++t) fp += F[i][t] * fP0[t][j];
+      fFP[i][j] = fp;
     }
-    D x[N], FP[N][N], P[N][N];
-    mv<N, N, D>(F, m0, x);
-    mm<N, N, N, D>(F, P0, FP);
-    sym_xyt_plus<N, N, D>(FP, F, Q, P);
-    D HP[M][N], S1[M][M], s1d[M];
-    mm<M, N, N, D>(H, P, HP);
-    sym_xyt_plus<M, N, D>(HP, H, Rm, S1);
-    chol_factor<M, D>(S1, s1d);
-    D K1t[M][N];
-    copy_mat<M, N, D>(HP, K1t);
-    chol_solve<M, N, D>(S1, s1d, K1t);
-    D Hx[M];
-    mv<M, N, D>(H, x, Hx);
+    if (l < N) {
+      D xv = D(0);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      D s = x[i];
-#pragma unroll
-      for (int t = 0; t < M; ++t) s -= K1t[t][i] * Hx[t];
-      cst[LY::c1 + i] = R(s);
-      cst[LY::m0 + i] = R(m0[i]);
-#pragma unroll
-      for (int t = 0; t < M; ++t) cst[LY::K1 + i * M + t] = R(K1t[t][i]);
+      for (int t = 0; t < N; ++t) xv += F[l][t] * fm0[t];
+      fx[l] = xv;
+      cst[LY::m0 + l] = R(fm0[l]);
     }
-    // C_1 = P - K1 S1 K1^T = P - (H P)^T S1^{-1} (H P)
+    if (l < M * N) cst[LY::H + l] = R(H[l / N][l % N]);
+    if (l < M * M) cst[LY::Rm + l] = R(0.5 * (Rm[l / M][l % M] + Rm[l % M][l / M]));
+    wave_lds_sync();
+    if (l < N * N) {  // P = F P0 F^T + Q
+      const int i = l / N, j = l % N, a = i < j ? i : j, b = i < j ? j : i;
+      D pv = Q[a][b];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+      for (int t = 0; t < N; ++t) pv += fFP[a][t] * F[b][t];
+      fP[i][j] = pv;
+    }
+    wave_lds_sync();
+    if (l < M * N) {  // H P
+      const int i = l / N, j = l % N;
+      D hp = D(0);
 #pragma unroll
-      for (int j = i; j < N; ++j) {
-        D s = P[i][j];
+      for (int t = 0; t < N; ++t) hp += H[i][t] * fP[t][j];
+      fHP[i][j] = hp;
+    }
+    if (l < M) {
+      D hx = D(0);
 #pragma unroll
-        for (int t = 0; t < M; ++t) s -= HP[t][i] * K1t[t][j];
-        cst[LY::C1 + i * N + j] = R(s);
-        cst[LY::C1 + j * N + i] = R(s);
+      for (int t = 0; t < N; ++t) hx += H[l][t] * fx[t];
+      fHx[l] = hx;
+    }
+    wave_lds_sync();
+    if (l < M * M) {  // S1 = H P H^T + R
+      const int i = l / M, j = l % M, a = i < j ? i : j, b = i < j ? j : i;
+      D sv = Rm[a][b];
+#pragma unroll
+      for (int t = 0; t < N; ++t) sv += fHP[a][t] * H[b][t];
+      fS[i][j] = sv;
+    }
+    wave_lds_sync();
+    if (l < N) {  // column l of K1^T = S1^{-1} H P
+      D Sr[M][M], sd[M], B[M][1];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) Sr[i][j] = fS[i][j];
+        B[i][0] = fHP[i][l];
       }
+      chol_factor<M, D>(Sr, sd);
+      chol_solve<M, 1, D>(Sr, sd, B);
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+      for (int i = 0; i < M; ++i) fK[i][l] = B[i][0];
+    }
+    wave_lds_sync();
+    if (l < N) {  // c1 = x - K1 H x
+      D cv = fx[l];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        cst[LY::F + i * N + j] = R(F[i][j]);
-        cst[LY::Q + i * N + j] = R(0.5 * (Q[i][j] + Q[j][i]));
-        cst[LY::P0 + i * N + j] = R(0.5 * (P0[i][j] + P0[j][i]));
-      }
+      for (int t = 0; t < M; ++t) cv -= fK[t][l] * fHx[t];
+      cst[LY::c1 + l] = R(cv);
+    }
+    if (l < N * M) cst[LY::K1 + (l / M) * M + l % M] = R(fK[l % M][l / M]);
+    if (l < N * N) {  // C_1 = P - (H P)^T S1^{-1} (H P)
+      const int i = l / N, j = l % N, a = i < j ? i : j, b = i < j ? j : i;
+      D cv = fP[a][b];
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) cst[LY::H + i * N + j] = R(H[i][j]);
-#pragma unroll
-      for (int j = 0; j < M; ++j) cst[LY::Rm + i * M + j] = R(0.5 * (Rm[i][j] + Rm[j][i]));
+      for (int t = 0; t < M; ++t) cv -= fHP[t][a] * fK[t][b];
+      cst[LY::C1 + l] = R(cv);
     }
   }
   // doubling, all in wavefront 0 (lanes synchronise among themselves); the
@@ -743,15 +802,31 @@ template <int N, class R> KF_DEV void st_store(R* p, const St<N, R>& s) {
   }
 }
 
+// A pipeline may scan its wavefronts itself (TableScan<Pipe>::value): it
+// then provides
+//   scan_wave(tid, lane)  fold + wavefront inclusive scan; returns the lane's
+//                         inclusive prefix (only the last lane's is used),
+//                         keeping what lane_prefix needs in its own LDS
+//   lane_prefix(tid)      the inclusive prefix of thread tid within its
+//                         wavefront, as an element
+// in place of the fold and of the generic wavefront scan below.
+template <class Pipe, class = void> struct TableScan {
+  static constexpr bool value = false;
+};
+template <class Pipe> struct TableScan<Pipe, std::void_t<decltype(Pipe::kTableScan)>> {
+  static constexpr bool value = Pipe::kTableScan;
+};
+
 template <class Pipe, int N, class R, int BLOCK, int L>
 KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   using E = typename Pipe::E;
+  constexpr bool TS = TableScan<Pipe>::value;
   constexpr int NW = BLOCK / WAVE;
   constexpr int PS = N + N * N;
   constexpr int ESW = E::SIZE * kWords<R>;  // tagged words per published element
   constexpr int PSW = PS * kWords<R>;       // tagged words per published anchored state
-  __shared__ E s_wt[NW];      // inclusive totals of each wavefront
-  __shared__ E s_x[BLOCK];    // inclusive prefix of each thread within its wavefront
+  __shared__ E s_wt[NW];               // inclusive totals of each wavefront
+  __shared__ E s_x[TS ? 1 : BLOCK];    // inclusive prefix of each thread within its wavefront
   __shared__ R s_pre[PS];     // the tile's exclusive anchored state
   __shared__ E s_part[NW];    // look-back: wavefront partials of a window
   __shared__ int s_lp[NW];    // look-back: first lane of each wavefront with a published prefix
@@ -806,7 +881,10 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   auto op = [&](const E& p, const E& q) { return pp.op(p, q); };
 
   // 1. thread fold
-  {
+  if constexpr (TS) {
+    E x = pp.scan_wave(tid, lane);
+    if (lane == WAVE - 1) s_wt[wid] = x;
+  } else {
     E x = pp.fold();
     // 2. wavefront scan, results through LDS
     wave_inclusive_scan(x, lane, op);
@@ -899,8 +977,14 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
 #pragma unroll 1
   for (int w = ws + 1; w < wid; ++w) pp.apply(st, s_wt[w]);
   if (lane > 0) {
-    if (decay_is_zero(s_x[tid - 1])) pp.anchor(s_x[tid - 1], st);
-    else pp.apply(st, s_x[tid - 1]);
+    if constexpr (TS) {
+      const E xp = pp.lane_prefix(tid - 1);
+      if (decay_is_zero(xp)) pp.anchor(xp, st);
+      else pp.apply(st, xp);
+    } else {
+      if (decay_is_zero(s_x[tid - 1])) pp.anchor(s_x[tid - 1], st);
+      else pp.apply(st, s_x[tid - 1]);
+    }
   }
   const bool have = (t > 0) || (tid > 0);
   pp.steps(st, have);
@@ -1025,10 +1109,54 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a,
 // valid steps are unaffected and the padded ones are not written.  The
 // per-step apply is the Kalman predict/update (kf_step).
 // ---------------------------------------------------------------------------
-template <int N, int M, class P, int L> struct FilterTiPipe {
+// Time-invariant forward scan.  Every thread aggregate covers L generic
+// elements, so the matrix part of any run of c consecutive thread
+// aggregates is the same in every wavefront and tile: S_{cL} (A, C, J of c*L
+// generic elements), and the vector part of a Lemma 1 combine of a run of a
+// aggregates with a later run of c is linear in the operands' vector parts,
+//   b = P1 b_x + P2 eta_y + b_y,   eta = P3 eta_y - P4 b_x + eta_x,
+// with coefficients P1..P4 that depend on (a, c) only (mpart_combine_lanes).
+// The wavefront scan (Hillis-Steele, offsets 2^d) only ever combines a run of
+// a = min(l - 2^d + 1, 2^d) aggregates with one of 2^d, so each workgroup
+// first builds S_{cL} for c = 1..64 and the coefficients of those 63 pairs
+// in LDS, level by level, 16 lanes per combine (in precision P::S, from the
+// FP64-derived S_L of the model constants); the threads then fold and scan
+// only the vector parts (b, eta), with no factorisation per lane.  A lane's
+// prefix is rebuilt as an element (S_{cL} with its vector part) where the
+// look-back and the exclusive states need one.
+template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
   using R = typename P::R;
+  using S = typename P::S;
   using E = FElem<N, R>;
   using LY = CL<N, M, L>;
+  static constexpr bool kTableScan = N * N <= 16;
+  static constexpr int NGRP = BLOCK / 16;  // 16-lane groups, one combine each
+  // Lanes read different entries of each table at once, so every entry is
+  // padded: consecutive entries then start in different LDS banks instead
+  // of all in the same one.  The coefficient rows are read as 16-byte
+  // vectors, so those entries are padded by 16 bytes and kept aligned.
+  struct Agg {
+    MPart<N, S> m;
+    S pad;
+  };
+  struct alignas(16) Coef {
+    S c[4][N][N];
+    S pad[16 / sizeof(S)];
+  };
+  struct Vec {
+    R v[2 * N];
+    R pad;
+  };
+  struct Tables {
+    Agg agg[WAVE];                    // agg[c - 1].m = S_{cL}
+    Coef coef[WAVE - 1];              // P1..P4 of (a, 2^d) at index 2^d - 1 + a - 1
+    S work[NGRP][4][N][N];            // combine scratch of each group
+    Vec v[BLOCK];                     // (b, eta) of each lane's inclusive prefix
+  };
+  KF_DEV static Tables& tables() {
+    __shared__ Tables t;
+    return t;
+  }
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
@@ -1050,6 +1178,105 @@ template <int N, int M, class P, int L> struct FilterTiPipe {
       for (int c = 0; c < M; ++c) yv[i][c] = (k0 + i < T) ? y[(k0 + i) * M + c] : R(0);
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
+  // S_{cL} as an element with vector part v = (b, eta)
+  KF_DEV static E with_vector(const MPart<N, S>& m, const R* v) {
+    E e;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      e.b[r] = v[r];
+      e.e[r] = v[N + r];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        e.A[r][j] = R(m.A[r][j]);
+        e.C[r][j] = R(m.C[r][j]);
+        e.J[r][j] = R(m.J[r][j]);
+      }
+    }
+    return e;
+  }
+  KF_DEV E scan_wave(int tid, int lane) const {
+    Tables& tb = tables();
+    // S_L from the model constants
+    if (tid < N * N) {
+      const int r = tid / N, j = tid % N;
+      tb.agg[0].m.A[r][j] = S(cst[LY::SL + r * N + j]);
+      tb.agg[0].m.C[r][j] = S(cst[LY::SL + N * N + r * N + j]);
+      tb.agg[0].m.J[r][j] = S(cst[LY::SL + 2 * N * N + r * N + j]);
+    }
+    __syncthreads();
+    // level d: S_{(a + h)L} = S_{aL} (x) S_{hL} and its coefficients, h = 2^d,
+    // a = 1..h; the inputs come from earlier levels
+    const int grp = tid >> 4, gl = tid & 15;
+#pragma unroll 1
+    for (int h = 1; h < WAVE; h <<= 1) {
+#pragma unroll 1
+      for (int a0 = 0; a0 < h; a0 += NGRP) {
+        const int a = a0 + grp + 1;
+        const bool act = a <= h;
+        const int ai = act ? a : 1;
+        mpart_combine_lanes<N, S>(tb.agg[ai - 1].m, tb.agg[h - 1].m, tb.agg[act ? ai + h - 1 : 0].m,
+                                  tb.coef[h - 1 + ai - 1].c, tb.work[grp], act ? gl : 16);
+      }
+      __syncthreads();
+    }
+    // fold and scan the vector parts
+    R b[N], e[N];
+    fold_vec(b, e);
+#pragma unroll 1
+    for (int h = 1; h < WAVE; h <<= 1) {
+      R ub[N], ue[N];
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        ub[r] = __shfl_up(b[r], h, WAVE);
+        ue[r] = __shfl_up(e[r], h, WAVE);
+      }
+      if (lane >= h) {
+        const int a = (lane - h + 1 < h) ? lane - h + 1 : h;
+        const S (&Pc)[4][N][N] = tb.coef[h - 1 + a - 1].c;
+        R nb[N], ne[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          S sb = S(b[r]), se = S(ue[r]);
+#pragma unroll
+          for (int t = 0; t < N; ++t) {
+            sb += Pc[0][r][t] * S(ub[t]) + Pc[1][r][t] * S(e[t]);
+            se += Pc[2][r][t] * S(e[t]) - Pc[3][r][t] * S(ub[t]);
+          }
+          nb[r] = R(sb);
+          ne[r] = R(se);
+        }
+        copy_vec<N, R>(nb, b);
+        copy_vec<N, R>(ne, e);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      tb.v[tid].v[r] = b[r];
+      tb.v[tid].v[N + r] = e[r];
+    }
+    return with_vector(tb.agg[lane].m, tb.v[tid].v);
+  }
+  KF_DEV E lane_prefix(int t) const {
+    Tables& tb = tables();
+    return with_vector(tb.agg[t & (WAVE - 1)].m, tb.v[t].v);
+  }
+  // vector part of the thread's aggregate of L generic elements
+  KF_DEV void fold_vec(R (&b)[N], R (&e)[N]) const {
+    const R* __restrict__ c = cst;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R sb = R(0), se = R(0);
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          sb += c[LY::PHI + i * N * M + r * M + q] * yv[i][q];
+          se += c[LY::PSI + i * N * M + r * M + q] * yv[i][q];
+        }
+      b[r] = sb;
+      e[r] = se;
+    }
+  }
   KF_DEV E fold() const {
     const R* __restrict__ c = cst;
     E e;
@@ -1154,8 +1381,8 @@ template <int N, int M, class P, int BLOCK, int L>
 __global__ __launch_bounds__(BLOCK) void k_filter_ti(ScanArgs<typename P::R> a,
                                                      KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
-  FilterTiPipe<N, M, P, L> pp(a, io);
-  scan_tile<FilterTiPipe<N, M, P, L>, N, typename P::R, BLOCK, L>(pp, a);
+  FilterTiPipe<N, M, P, L, BLOCK> pp(a, io);
+  scan_tile<FilterTiPipe<N, M, P, L, BLOCK>, N, typename P::R, BLOCK, L>(pp, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -455,27 +455,24 @@ KF_DEV void mpart_combine_lanes(const MPart<N, T>& x, const MPart<N, T>& y, MPar
   wave_lds_sync();
   if (on) W[3][r][c] = cofactor<N, T>(W[0], r, c);
   wave_lds_sync();
-  T idet = T(0);
   if (on) {
+    // det(M) by the first row, then with M^{-1} = adj(M) / det(M) and
+    // adj(M)[a][b] = cofactor (b, a):  Z = M^{-1} A_x, Y = M^{-1} C_x,
+    // P1 = A_y M^{-1}
     T det = T(0);
 #pragma unroll
     for (int t = 0; t < N; ++t) det += W[0][0][t] * W[3][0][t];
-    idet = krcp(det);
-  }
-  wave_lds_sync();
-  if (on) W[0][c][r] = W[3][r][c] * idet;  // M^{-1} = adj(M) / det(M)
-  wave_lds_sync();
-  if (on) {
+    const T idet = krcp(det);
     T zr = T(0), yr = T(0), pr = T(0);
 #pragma unroll
     for (int t = 0; t < N; ++t) {
-      zr += W[0][r][t] * x.A[t][c];
-      yr += W[0][r][t] * x.C[t][c];
-      pr += y.A[r][t] * W[0][t][c];
+      zr += W[3][t][r] * x.A[t][c];
+      yr += W[3][t][r] * x.C[t][c];
+      pr += y.A[r][t] * W[3][c][t];
     }
-    W[1][r][c] = zr;  // Z
-    W[2][r][c] = yr;  // Y
-    Pc[0][r][c] = pr;
+    W[1][r][c] = zr * idet;  // Z
+    W[2][r][c] = yr * idet;  // Y
+    Pc[0][r][c] = pr * idet;
   }
   wave_lds_sync();
   if (on) {
