@@ -1108,8 +1108,8 @@ __global__ __launch_bounds__(BLOCK) void k_filter(ScanArgs<typename P::R> a,
 // past T are padded with y = 0; the filter is causal, so the outputs at
 // valid steps are unaffected and the padded ones are not written.  The
 // per-step apply is the Kalman predict/update (kf_step).
-// ---------------------------------------------------------------------------
-// Time-invariant forward scan.  Every thread aggregate covers L generic
+//
+// The same holds one level up.  Every thread aggregate covers L generic
 // elements, so the matrix part of any run of c consecutive thread
 // aggregates is the same in every wavefront and tile: S_{cL} (A, C, J of c*L
 // generic elements), and the vector part of a Lemma 1 combine of a run of a
@@ -1153,10 +1153,22 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
     S work[NGRP][4][N][N];            // combine scratch of each group
     Vec v[BLOCK];                     // (b, eta) of each lane's inclusive prefix
   };
-  KF_DEV static Tables& tables() {
-    __shared__ Tables t;
-    return t;
+  // Output staging of the step walk: each wavefront's rows of SB consecutive
+  // steps per lane (RW scalars each, lane l's rows padded by l scalars so
+  // that the lanes' rows start in different banks).  The walk starts after
+  // the last read of the tables, so the two share their LDS.
+  static constexpr int RW = N + N * N;
+  static constexpr int SB = (sizeof(R) == 4 ? 4 : 2) < L ? (sizeof(R) == 4 ? 4 : 2) : L;
+  static constexpr int STG = WAVE * SB * RW + WAVE;
+  union Shared {
+    Tables t;
+    R stg[BLOCK / WAVE][STG];
+  };
+  KF_DEV static Shared& shared() {
+    __shared__ Shared sh;
+    return sh;
   }
+  KF_DEV static Tables& tables() { return shared().t; }
   const ScanArgs<R>& a;
   const IO<R>& io;
   long T, k0;
@@ -1324,6 +1336,12 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
       for (int j = 0; j < N; ++j) v.C[i][j] = st.m[i][j];
     }
   }
+  // The walk: L Kalman steps per thread, in blocks of SB steps.  The
+  // outputs of a block are staged in LDS and then leave in whole runs: the
+  // rows of lane g's block are contiguous in memory (SB rows), and the
+  // wavefront stores them with consecutive lanes on consecutive chunks of up
+  // to 16 bytes, so each store instruction writes few, whole lines instead
+  // of one piece of 64 different lines.
   KF_DEV void steps(St<N, R>& st, bool) const {
     R F[N][N], Q[N][N], H[M][N], Rm[M][M];
 #pragma unroll
@@ -1340,38 +1358,54 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
 #pragma unroll
       for (int j = 0; j < M; ++j) Rm[i][j] = cst[LY::Rm + i * M + j];
     }
-    // outputs leave in whole 128-byte lines where the sizes allow: the means
-    // of MG consecutive steps, the covariances of PG consecutive steps
-    constexpr int MG = (N * (int)sizeof(R) <= 128 && 128 % (N * (int)sizeof(R)) == 0 &&
-                        L % (128 / (N * (int)sizeof(R))) == 0) ? 128 / (N * (int)sizeof(R)) : 1;
-    constexpr int PG = (N * N * (int)sizeof(R) <= 128 && 128 % (N * N * (int)sizeof(R)) == 0 &&
-                        L % (128 / (N * N * (int)sizeof(R))) == 0) ? 128 / (N * N * (int)sizeof(R)) : 1;
-    R ov[MG][N], om[PG][N][N];
+    __syncthreads();  // every lane is done with the tables
+    const int lane = threadIdx.x & (WAVE - 1);
+    R* stg = shared().stg[threadIdx.x / WAVE];
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-      const long k = k0 + i;
-      if (k < T) kf_step<N, M, P>(st.v, st.m, F, Q, H, Rm, yv[i]);
-      copy_vec<N, R>(st.v, ov[i % MG]);
-      copy_mat<N, N, R>(st.m, om[i % PG]);
-      if (i % PG == PG - 1) {
+    for (int s0 = 0; s0 < L; s0 += SB) {
 #pragma unroll
-        for (int j = 0; j < PG; ++j) {
-          const long kj = k - (PG - 1) + j;
-          if (kj < T)
+      for (int i = 0; i < SB; ++i) {
+        if (k0 + s0 + i < T) kf_step<N, M, P>(st.v, st.m, F, Q, H, Rm, yv[s0 + i]);
+        R* row = stg + (lane * SB + i) * RW + lane;
 #pragma unroll
-            for (int r = 0; r < N; ++r)
+        for (int r = 0; r < N; ++r) {
+          row[r] = st.v[r];
 #pragma unroll
-              for (int cc = 0; cc < N; ++cc) st_out(&Po[kj * N * N + r * N + cc], om[j][r][cc]);
+          for (int c = 0; c < N; ++c) row[N + r * N + c] = st.m[r][c];
         }
       }
-      if (i % MG == MG - 1) {
+      wave_lds_sync();
+      store_block<N * N, N>(stg, s0, Po);
+      store_block<N, 0>(stg, s0, mo);
+      wave_lds_sync();
+    }
+  }
+  // chunk of a run of W-scalar rows: up to 16 bytes, dividing the row
+  template <int W> static constexpr int chunk() {
+    return (W * (int)sizeof(R)) % 16 == 0 ? 16 / (int)sizeof(R)
+           : (W * (int)sizeof(R)) % 8 == 0 ? (8 / (int)sizeof(R) > 0 ? 8 / (int)sizeof(R) : 1)
+                                           : 1;
+  }
+  // Store the staged block (steps s0 .. s0+SB-1 of every lane of the
+  // wavefront) of the output with W scalars per row, found at scalar OFF of
+  // each staged row.
+  template <int W, int OFF> KF_DEV void store_block(const R* stg, int s0, R* out) const {
+    constexpr int CH = chunk<W>();
+    constexpr int PER = SB * W / CH;  // chunks per lane's run
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long wk0 = k0 - (long)lane * L;  // first row of the wavefront
 #pragma unroll
-        for (int j = 0; j < MG; ++j) {
-          const long kj = k - (MG - 1) + j;
-          if (kj < T)
+    for (int j = 0; j < PER; ++j) {
+      const int c = j * WAVE + lane;
+      const int g = c / PER, o = (c % PER) * CH;
+      const int row = o / W, e = o % W;
+      const long k = wk0 + (long)g * L + s0 + row;
+      if (k < T) {
+        const R* q = stg + (g * SB + row) * RW + g + OFF + e;
+        R v[CH];
 #pragma unroll
-            for (int r = 0; r < N; ++r) st_out(&mo[kj * N + r], ov[j][r]);
-        }
+        for (int t = 0; t < CH; ++t) v[t] = q[t];
+        __builtin_memcpy(out + k * W + e, v, sizeof(v));
       }
     }
   }
