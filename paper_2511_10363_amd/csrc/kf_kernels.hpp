@@ -817,6 +817,20 @@ template <class Pipe> struct TableScan<Pipe, std::void_t<decltype(Pipe::kTableSc
   static constexpr bool value = Pipe::kTableScan;
 };
 
+// A pipeline may also stage its loads and stores through LDS
+// (StagesOut<Pipe>::value): its fold and its step walk then take the LDS of
+// the per-thread wavefront prefixes as scratch (kStageBytes at most), each
+// wavefront only the part that holds its own lanes' prefixes (so a
+// wavefront that has finished its fold and scan never overwrites the
+// scratch of one still folding), and the walk only after a workgroup
+// barrier (the exclusive states have then been read).
+template <class Pipe, class = void> struct StagesOut {
+  static constexpr bool value = false;
+};
+template <class Pipe> struct StagesOut<Pipe, std::void_t<decltype(Pipe::kStageBytes)>> {
+  static constexpr bool value = true;
+};
+
 template <class Pipe, int N, class R, int BLOCK, int L>
 KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   using E = typename Pipe::E;
@@ -885,7 +899,9 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
     E x = pp.scan_wave(tid, lane);
     if (lane == WAVE - 1) s_wt[wid] = x;
   } else {
-    E x = pp.fold();
+    E x;
+    if constexpr (StagesOut<Pipe>::value) x = pp.fold(reinterpret_cast<typename Pipe::R*>(s_x));
+    else x = pp.fold();
     // 2. wavefront scan, results through LDS
     wave_inclusive_scan(x, lane, op);
     s_x[tid] = x;
@@ -987,7 +1003,12 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
     }
   }
   const bool have = (t > 0) || (tid > 0);
-  pp.steps(st, have);
+  if constexpr (StagesOut<Pipe>::value) {
+    static_assert(TS || Pipe::kStageBytes <= sizeof(s_x), "staging exceeds the prefix buffer");
+    pp.steps(st, have, reinterpret_cast<typename Pipe::R*>(s_x));
+  } else {
+    pp.steps(st, have);
+  }
   finish_grid(a.ctr, tag);
 }
 
@@ -1513,29 +1534,13 @@ template <int N, int M, class P, int L, int B, bool TV = false> struct RtsPipe {
   }
   // Steps are walked last to first in groups of PG consecutive rows whose
   // covariances fill one 128-byte line (two rows at nx = 4 in FP32), with the
-  // next (earlier) group already in flight, so each line is fetched once and
-  // consumed at once.
-  // In FP32 a thread's L filtered means (one 128-byte line at nx = 4) are
-  // read once into an LDS column of its own, serve both walks, and are
-  // overwritten in place by the smoothed means, which leave as one line.
+  // next (earlier) group already in flight.  In FP32 a thread's L filtered
+  // means are read once into an LDS column of its own, serve both walks, and
+  // are overwritten in place by the smoothed means.
   static constexpr int PG = (N * N * (int)sizeof(R) <= 64 && L % 2 == 0) ? 2 : 1;
   static constexpr int NG = L / PG;
   static constexpr bool MLDS = (sizeof(R) == 4);
   R* ms;  // this thread's column: row i, component c at ms[(i * N + c) * B]
-  KF_DEV void load_group(long kb, R (&x)[PG][N], R (&Pk)[PG][N][N]) const {
-#pragma unroll
-    for (int i = 0; i < PG; ++i) {
-      const long k = kb + i;
-      if (k >= 0 && k < T) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          if (!MLDS) x[i][r] = mf[k * N + r];
-#pragma unroll
-          for (int c = 0; c < N; ++c) Pk[i][r][c] = Pf[k * N * N + r * N + c];
-        }
-      }
-    }
-  }
   KF_DEV void mean_rows(long kb, int ib, R (&x)[PG][N]) const {
     if (MLDS) {
 #pragma unroll
@@ -1544,29 +1549,122 @@ template <int N, int M, class P, int L, int B, bool TV = false> struct RtsPipe {
         for (int r = 0; r < N; ++r) x[i][r] = ms[((ib + i) * N + r) * B];
     }
   }
-  KF_DEV E fold() {
+  // Filtered covariances are read a group at a time by the whole
+  // wavefront: each lane's PG rows are contiguous in memory, so the
+  // wavefront loads them with consecutive lanes on consecutive 16-byte
+  // chunks (whole lines per load instruction) into registers, one group
+  // ahead, and passes them through its LDS staging to the lanes that own
+  // them.  In FP32 the wavefront's filtered means (64 * L consecutive rows)
+  // are read the same way into the threads' LDS columns.
+  static constexpr int CHP = (N * N * (int)sizeof(R)) % 16 == 0 ? 16 / (int)sizeof(R)
+                             : ((N * N * (int)sizeof(R)) % 8 == 0 && sizeof(R) == 4) ? 2
+                                                                                   : 1;
+  static constexpr int PERP = PG * N * N / CHP;  // chunks of a lane's group, one per load pass
+  // A load pass covers LPP lanes' groups, PERP lanes each (the last lanes
+  // idle when PERP does not divide 64): in pass j, lane sub * PERP + q takes
+  // chunk q of lane l = j * LPP + sub, whose rows start LPP * L rows lower
+  // for every further pass -- one base address per lane and a fixed stride
+  // between passes.
+  static constexpr int LPP = WAVE / PERP;
+  static constexpr int NP = (WAVE + LPP - 1) / LPP;  // load passes per group
+  KF_DEV void fetch_group(int g, R (&buf)[NP][CHP]) const {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int sub = lane / PERP, o = (lane % PERP) * CHP;
+    const long kb = lane_k0(sub) + g * PG + o / NN;  // pass 0
+    const R* src = Pf + kb * NN + o % NN;
+    constexpr long STEP = (long)LPP * L * NN;  // scalars between passes
+    // all rows below T unless this is the sequence's last tile
+    const bool all = uniform(lane_k0(0) + L - 1) < T;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const bool act = sub < LPP && j * LPP + sub < WAVE;
+      if (act && (all || kb - (long)j * LPP * L < T)) {
+        __builtin_memcpy(buf[j], src - j * STEP, sizeof(buf[j]));
+      } else {
+#pragma unroll
+        for (int t = 0; t < CHP; ++t) buf[j][t] = R(0);
+      }
+    }
+  }
+  // put the fetched chunks in the staging rows, then read this lane's rows
+  KF_DEV void unstage_group(R* stg, const R (&buf)[NP][CHP], R (&Pk)[PG][N][N]) const {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int sub = lane / PERP, o = (lane % PERP) * CHP;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int l = j * LPP + sub;
+      if (sub < LPP && l < WAVE) {
+        R* q = stg + (l * PG + o / NN) * NN + l + o % NN;
+#pragma unroll
+        for (int t = 0; t < CHP; ++t) q[t] = buf[j][t];
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < PG; ++i)
+#pragma unroll
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) Pk[i][r][c] = stg[(lane * PG + i) * NN + lane + r * N + c];
+    wave_lds_sync();
+  }
+  KF_DEV void load_means() {
+    __shared__ R s_mean[MLDS ? L * N * B : 1];
+    ms = s_mean + threadIdx.x;
+    constexpr int CH = chunk<N>();
+    constexpr int PER = N / CH;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long base = lane_k0(WAVE - 1);
+    R* col0 = ms - lane;
+#pragma unroll
+    for (int j = 0; j < L * PER; ++j) {
+      const int c = j * WAVE + lane;
+      const int rr = c / PER, e = (c % PER) * CH;
+      const long k = base + rr;
+      const int l = WAVE - 1 - rr / L, i = rr % L;
+      R v[CH];
+      if (k < T) {
+        __builtin_memcpy(v, mf + k * N + e, sizeof(v));
+      } else {
+#pragma unroll
+        for (int t = 0; t < CH; ++t) v[t] = R(0);
+      }
+#pragma unroll
+      for (int t = 0; t < CH; ++t) col0[(i * N + e + t) * B + l] = v[t];
+    }
+    wave_lds_sync();
+  }
+  KF_DEV void load_x(int g, R (&x)[PG][N]) const {
+#pragma unroll
+    for (int i = 0; i < PG; ++i) {
+      const long k = k0 + g * PG + i;
+#pragma unroll
+      for (int r = 0; r < N; ++r) x[i][r] = (k < T) ? mf[k * N + r] : R(0);
+    }
+  }
+  KF_DEV E fold(R* stage) {
     E agg;
     set_identity(agg);
-    R xn[PG][N], Pn[PG][N][N];
-    load_group(k0 + (NG - 1) * PG, xn, Pn);
-    if (MLDS) {
-      __shared__ R s_mean[MLDS ? L * N * B : 1];
-      ms = s_mean + threadIdx.x;
-#pragma unroll
-      for (int i = 0; i < L; ++i)
-#pragma unroll
-        for (int r = 0; r < N; ++r) ms[(i * N + r) * B] = (k0 + i < T) ? mf[(k0 + i) * N + r] : R(0);
-    }
+    R* stg = stage + (threadIdx.x / WAVE) * WSTR;
+    R buf[NP][CHP], xn[PG][N];
+    fetch_group(NG - 1, buf);
+    if (MLDS) load_means();
+    else load_x(NG - 1, xn);
 #pragma unroll 1
     for (int g = NG - 1; g >= 0; --g) {
       R x[PG][N], Pk[PG][N][N];
+      unstage_group(stg, buf, Pk);
+      if (MLDS) {
+        if (g > 0) fetch_group(g - 1, buf);
+        mean_rows(k0 + g * PG, g * PG, x);
+      } else {
 #pragma unroll
-      for (int i = 0; i < PG; ++i) {
-        copy_vec<N, R>(xn[i], x[i]);
-        copy_mat<N, N, R>(Pn[i], Pk[i]);
+        for (int i = 0; i < PG; ++i) copy_vec<N, R>(xn[i], x[i]);
+        if (g > 0) {
+          fetch_group(g - 1, buf);
+          load_x(g - 1, xn);
+        }
       }
-      if (g > 0) load_group(k0 + (g - 1) * PG, xn, Pn);
-      mean_rows(k0 + g * PG, g * PG, x);
 #pragma unroll
       for (int i = PG - 1; i >= 0; --i) {
         const long k = k0 + g * PG + i;
@@ -1591,59 +1689,125 @@ template <int N, int M, class P, int L, int B, bool TV = false> struct RtsPipe {
       for (int j = 0; j < N; ++j) v.L[i][j] = st.m[i][j];
     }
   }
-  // Same grouping as fold(); a group's outputs are written together, in row
-  // order, once its rows are done.
-  KF_DEV void steps(St<N, R>& st, bool) const {
-    R xn[PG][N], Pn[PG][N][N];
-    load_group(k0 + (NG - 1) * PG, xn, Pn);
+  // Same grouping as fold().  A group's smoothed covariances (PG rows per
+  // lane, contiguous in memory) are staged in LDS and stored by the whole
+  // wavefront with consecutive lanes on consecutive 16-byte chunks, so each
+  // store instruction writes whole lines; in FP32 the smoothed means collect
+  // in the thread's LDS column and leave at the end as one contiguous run per
+  // wavefront (its 64 threads own 64 * L consecutive rows).
+  static constexpr int NN = N * N;
+  static constexpr int STG = WAVE * PG * NN + WAVE;  // per wavefront, lane rows padded by lane
+  // a wavefront's staging starts where its lanes' wavefront prefixes do
+  static constexpr int WSTR = WAVE * (int)sizeof(E) / (int)sizeof(R);
+  static_assert(STG <= WSTR, "staging of a wavefront exceeds its prefix slots");
+  static constexpr size_t kStageBytes = (size_t)(B / WAVE) * WSTR * sizeof(R);
+  template <int W> static constexpr int chunk() {
+    return (W * (int)sizeof(R)) % 16 == 0 ? 16 / (int)sizeof(R)
+           : ((W * (int)sizeof(R)) % 8 == 0 && sizeof(R) == 4) ? 2
+                                                               : 1;
+  }
+  KF_DEV void steps(St<N, R>& st, bool, R* stage) const {
+    __syncthreads();  // every lane has read its prefix from the staging space
+    const int lane = threadIdx.x & (WAVE - 1);
+    R* stg = stage + (threadIdx.x / WAVE) * WSTR;
+    R buf[NP][CHP], xn[PG][N];
+    fetch_group(NG - 1, buf);
+    if (!MLDS) load_x(NG - 1, xn);
 #pragma unroll 1
     for (int g = NG - 1; g >= 0; --g) {
       R x[PG][N], Pk[PG][N][N];
+      unstage_group(stg, buf, Pk);
+      if (MLDS) {
+        if (g > 0) fetch_group(g - 1, buf);
+        mean_rows(k0 + g * PG, g * PG, x);
+      } else {
 #pragma unroll
-      for (int i = 0; i < PG; ++i) {
-        copy_vec<N, R>(xn[i], x[i]);
-        copy_mat<N, N, R>(Pn[i], Pk[i]);
+        for (int i = 0; i < PG; ++i) copy_vec<N, R>(xn[i], x[i]);
+        if (g > 0) {
+          fetch_group(g - 1, buf);
+          load_x(g - 1, xn);
+        }
       }
-      if (g > 0) load_group(k0 + (g - 1) * PG, xn, Pn);
-      mean_rows(k0 + g * PG, g * PG, x);
-      R ov[PG][N], om[PG][N][N];
 #pragma unroll
       for (int i = PG - 1; i >= 0; --i) {
         const long k = k0 + g * PG + i;
         if (k < T) sapply<N, P>(element(k, x[i], Pk[i]), st.v, st.m);
-        copy_vec<N, R>(st.v, ov[i]);
-        copy_mat<N, N, R>(st.m, om[i]);
-      }
+        R* row = stg + (lane * PG + i) * NN + lane;
 #pragma unroll
-      for (int i = 0; i < PG; ++i) {
-        const long k = k0 + g * PG + i;
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+          for (int c = 0; c < N; ++c) row[r * N + c] = st.m[r][c];
         if (MLDS) {
 #pragma unroll
-          for (int r = 0; r < N; ++r) ms[((g * PG + i) * N + r) * B] = ov[i][r];
-        }
-        if (k < T) {
+          for (int r = 0; r < N; ++r) ms[((g * PG + i) * N + r) * B] = st.v[r];
+        } else if (k < T) {
 #pragma unroll
-          for (int r = 0; r < N; ++r) {
-            if (!MLDS) st_out(&mo[k * N + r], ov[i][r]);
-#pragma unroll
-            for (int c = 0; c < N; ++c) st_out(&Po[k * N * N + r * N + c], om[i][r][c]);
-          }
+          for (int r = 0; r < N; ++r) st_out(&mo[k * N + r], st.v[r]);
         }
       }
+      wave_lds_sync();
+      store_cov_group(stg, g);
+      wave_lds_sync();
     }
-    if (MLDS) {
+    if (MLDS) store_means();
+  }
+  // Lane l of this wavefront holds rows k0(l) .. k0(l) + L - 1 with
+  // k0(l) = k0 + (lane - l) * L (the walk's threads run in descending
+  // time), so row k0(l) + j is row (63 - l) * L + j of the wavefront's run.
+  KF_DEV long lane_k0(int l) const {
+    const int lane = threadIdx.x & (WAVE - 1);
+    return k0 + (long)(lane - l) * L;
+  }
+  KF_DEV void store_cov_group(const R* stg, int g) const {
+    constexpr int CH = chunk<NN>();
+    constexpr int PER = PG * NN / CH;
+    const int lane = threadIdx.x & (WAVE - 1);
 #pragma unroll
-      for (int i = 0; i < L; ++i)
-        if (k0 + i < T) {
+    for (int j = 0; j < PER; ++j) {
+      const int c = j * WAVE + lane;
+      const int l = c / PER, o = (c % PER) * CH;
+      const int row = o / NN, e = o % NN;
+      const long k = lane_k0(l) + g * PG + row;
+      if (k < T) {
+        const R* q = stg + (l * PG + row) * NN + l + e;
+        R v[CH];
 #pragma unroll
-          for (int r = 0; r < N; ++r) st_out(&mo[(k0 + i) * N + r], ms[(i * N + r) * B]);
-        }
+        for (int t = 0; t < CH; ++t) v[t] = q[t];
+        __builtin_memcpy(Po + k * NN + e, v, sizeof(v));
+      }
+    }
+  }
+  // FP32 smoothed means, from the LDS columns of the wavefront's threads:
+  // the wavefront's rows are contiguous, row r of the run belongs to the
+  // thread whose k0 is the largest not above it.
+  KF_DEV void store_means() const {
+    constexpr int CH = chunk<N>();
+    constexpr int PER = N / CH;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long base = lane_k0(WAVE - 1);  // lowest row of the wavefront
+    const R* col0 = ms - lane;            // column of lane 0 of this wavefront
+#pragma unroll
+    for (int j = 0; j < L * PER; ++j) {
+      const int c = j * WAVE + lane;
+      const int rr = c / PER, e = (c % PER) * CH;
+      const long k = base + rr;
+      const int l = WAVE - 1 - rr / L, i = rr % L;
+      if (k < T) {
+        R v[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) v[t] = col0[((i * N + e + t) * B) + l];
+        __builtin_memcpy(mo + k * N + e, v, sizeof(v));
+      }
     }
   }
 };
 
+// Two workgroups per CU in FP32 (the grid of the long sequences is two
+// tiles per CU); the wider precisions keep the register budget of one.
+template <class P> constexpr int rts_min_blocks() { return sizeof(typename P::S) == 4 ? 2 : 1; }
+
 template <int N, int M, class P, int BLOCK, int L, bool TV = false>
-__global__ __launch_bounds__(BLOCK) void k_rts(ScanArgs<typename P::R> a, TvModel<typename P::R> tv,
+__global__ __launch_bounds__(BLOCK, rts_min_blocks<P>()) void k_rts(ScanArgs<typename P::R> a, TvModel<typename P::R> tv,
                                                KFS_IO_PARAMS(typename P::R)) {
   KFS_IO_MAKE(typename P::R);
   RtsPipe<N, M, P, L, BLOCK, TV> pp(a, io, tv);
