@@ -218,11 +218,13 @@ def main() -> int:
     t_filt = np.array([e[1].elapsed_time(e[2]) for e in events])
     t_back = np.array([e[2].elapsed_time(e[3]) for e in events])
 
-    # algorithmic bytes per launch: forward pass reads y and writes the filter
-    # moments, the backward pass writes the smoothed moments; their sum is the
-    # job's compulsory traffic w (m + 2n + 2n^2) per step
+    # algorithmic bytes per launch: each kernel's compulsory reads and writes,
+    # once each.  The forward pass reads y and writes the filter moments; the
+    # RTS pass reads the filter moments and writes the smoothed ones; the
+    # two-filter pass also reads y.  The job as a whole moves w (m + 2n + 2n^2)
+    # per step (job_hbm_frac).
     bytes_filter = T * w * (m + n + n * n)
-    bytes_back = T * w * (n + n * n)
+    bytes_back = T * w * (2 * (n + n * n) + (m if args.smoother == "tf" else 0))
     kern = {"k_filter": (float(t_filt.mean()), bytes_filter),
             kback: (float(t_back.mean()), bytes_back)}
     dom = max(kern, key=lambda k: kern[k][0])
@@ -287,6 +289,7 @@ def main() -> int:
         "kernel_ms": {"k_prepare": float(t_prep.mean()), "k_filter": float(t_filt.mean()),
                       kback: float(t_back.mean())},
         "job_hbm_frac": value * w * (m + 2 * n + 2 * n * n) / (HBM_PEAK_GBS * 1e9),
+        "kernel_hbm_frac": {k: b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS for k, (t, b) in kern.items()},
         "copy_GBps": copy_gbps,
         "graph_ms_per_step": graph_ms,
         "errors_vs_oracle": errors,
