@@ -17,13 +17,17 @@ constexpr int kBlock = 256;
 // largest power of two L <= the maximum (and >= 2) that still gives a target
 // number of tiles.  The time-invariant filter aims at 256 tiles, one per CU,
 // since its fold is cheap and its wavefront totals become anchors early.  The
-// full-element scans keep the longest tiles unless a sequence would have fewer
-// than 4: their tile aggregates must be long to underflow into anchors (see
-// decay_is_zero), and a short-tile look-back over non-anchored aggregates
-// costs more than the parallelism gained.
+// backward scans (RTS, two-filter) aim at 256 tiles too: at T = 2^18 their
+// 8-step tiles would leave half the CUs idle (measured on MI355X, 4-step
+// tiles: RTS 47.6 -> 37.5 us in FP32, two-filter 87.6 -> 63.4 us in the mixed
+// mode), while at T = 2^20 the 8-step tiles already give two per CU.  The
+// generic forward scan keeps the longest tiles unless a sequence would have
+// fewer than 4: its tile aggregates must be long to underflow into anchors
+// (see decay_is_zero), and a short-tile look-back over non-anchored
+// aggregates costs more than the parallelism gained.
 constexpr int items_per_thread(int nx) { return nx <= 2 ? 16 : (nx <= 4 ? 8 : 4); }
 constexpr int items_ti(int nx) { return nx <= 4 ? 16 : 8; }
-constexpr long kTilesTi = 256, kTilesScan = 4;
+constexpr long kTilesTi = 256, kTilesScan = 4, kTilesBack = 256;
 
 inline long ntiles_for(long T, int items) {
   const long tile = (long)kBlock * items;
@@ -210,7 +214,7 @@ inline Layout make_layout(const Job& j) {
       L.items[0] = j.batch ? lf
                            : choose_items(T, nseq, lf,
                                           scan == KF_SCAN_LOOKBACK_GENERIC ? kTilesScan : kTilesTi);
-      L.items[1] = j.batch ? lb : choose_items(T, nseq, lb, kTilesScan);
+      L.items[1] = j.batch ? lb : choose_items(T, nseq, lb, kTilesBack);
     }
     for (int s = 0; s < 2; ++s) L.tile[s] = (long)kBlock * L.items[s];
   }
