@@ -306,14 +306,15 @@ def other_configs(args, np, torch, W, kfscan, dev) -> dict:
     two-filter smoother in FP32 storage with FP64 solves.  Each: event-timed
     passes (prepare + forward + backward, median of 50 after 5 warm-up) and,
     with the CPU-baseline leg on, the errors against the FP64 sequential RTS
-    smoother of the oracle."""
-    import oracle
+    smoother of the oracle.  Then the generic look-back filter and the paper's
+    time-varying model at T = 2^20 in FP32."""
+    if args.cpu_seconds > 0:
+        import oracle
 
     res = {}
-    for name, T, prec, back, oracle_fn in (
-            ("T1000_f64_filter_rts", 1000, "f64", "kf_pass_rts", oracle.smooth_rts),
-            ("T2^18_mixed_filter_twofilter", 1 << 18, "mixed", "kf_pass_twofilter",
-             oracle.smooth_rts)):
+    for name, T, prec, back in (
+            ("T1000_f64_filter_rts", 1000, "f64", "kf_pass_rts"),
+            ("T2^18_mixed_filter_twofilter", 1 << 18, "mixed", "kf_pass_twofilter")):
         model, y_np = W.tracking(T, seed=args.seed)
         dt = kfscan.dtype_for(prec)
         dmodel = kfscan.model_to_device(model.arrays(), prec, dev)
@@ -344,13 +345,65 @@ def other_configs(args, np, torch, W, kfscan, dev) -> dict:
         if prec != "f64":
             cast = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
             arrs, yy = tuple(cast(a) for a in arrs), cast(y_np)
-        ref = oracle_fn(*arrs, yy)
+        ref = oracle.smooth_rts(*arrs, yy)
         got = [t[0].double().cpu().numpy() for t in plan.outputs()]
         errs = {k: float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300))
                 for k, g, r in zip(("m_filt", "P_filt", "m_smooth", "P_smooth"), got, ref)}
         errs["z_smooth_max"] = float(np.max(np.abs(got[2] - ref[2]) /
                                             np.sqrt(np.einsum("kii->ki", ref[3]))))
         res[name]["errors_vs_fp64_rts_oracle"] = errs
+
+    # the generic look-back filter (full Lemma 1 elements, no time-invariant
+    # tables) on the headline workload, and the paper's time-varying model
+    # (Sec. VI-A, per-step F, Q, H, R, u, d streamed from HBM): T = 2^20, FP32
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def rel(got, ref):
+        return {k: float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300))
+                for k, g, r in zip(("m_filt", "P_filt", "m_smooth", "P_smooth"), got, ref)}
+
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+    T = 1 << 20
+    model, y_np = W.tracking(T, seed=args.seed)
+    dmodel = kfscan.model_to_device(model.arrays(), "f32", dev)
+    y = torch.as_tensor(y_np).to(dev, torch.float32).contiguous()
+    plan = kfscan.Plan(dmodel, y, precision="f32", scan="lookback_generic", smoother=True)
+    ms = timed(lambda: (plan("kf_prepare"), plan("kf_pass_filter"), plan("kf_pass_rts")))
+    res["T2^20_f32_generic_lookback_filter_rts"] = {"ms_per_pass": ms, "steps_per_s": T / (ms * 1e-3)}
+    if args.cpu_seconds > 0:
+        ref = oracle.smooth_rts(*(f32(a) for a in model.arrays()), f32(y_np))
+        res["T2^20_f32_generic_lookback_filter_rts"]["errors_vs_fp64_rts_oracle"] = rel(
+            [t[0].double().cpu().numpy() for t in plan.outputs()], ref)
+    del plan, y, dmodel
+
+    rng = np.random.default_rng(args.seed)
+    tv = W.paper_tv_model(T, rng, 4, 2)
+    ytv = W.simulate(tv, T, rng)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(dev, torch.float32).contiguous()  # noqa: E731
+    targs = [dv(a) for a in (tv.F, tv.Q, tv.H, tv.R, tv.u, tv.d, tv.m0, tv.P0, ytv)]
+    outs = [None]
+
+    def run_tv():
+        outs[0] = kfscan.tv("rts", *targs, precision="f32")
+    ms = timed(run_tv)
+    res["paper_tv_T2^20_f32_filter_rts"] = {"ms_per_pass": ms, "steps_per_s": T / (ms * 1e-3)}
+    if args.cpu_seconds > 0:
+        ref = oracle.smooth_rts(*(f32(a) for a in (tv.F, tv.Q, tv.H, tv.R, tv.m0, tv.P0)), f32(ytv),
+                                f32(tv.u), f32(tv.d))
+        res["paper_tv_T2^20_f32_filter_rts"]["errors_vs_fp64_rts_oracle"] = rel(
+            [o.double().cpu().numpy() for o in outs[0]], ref)
     return res
 
 
