@@ -960,12 +960,18 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
       tag_load<R>(sp, a.pre + (base + idx) * PSW, tag, a.ctr + 2);
       pp.expand(sp, v);
     };
+    auto try_expand = [&](long idx, E& v) {
+      St<N, R> sp;
+      const bool ok = tag_try_load<R>(sp, a.pre + (base + idx) * PSW, tag);
+      pp.expand(sp, v);
+      return ok;
+    };
     // tiles per thread in a look-back window: one window of BLOCK*G tiles
     // reaches back over a whole sequence of up to 4*BLOCK tiles
     const long g = (si.ntiles + BLOCK - 1) / BLOCK;
     const int G = (int)(g < 1 ? 1 : (g > 4 ? 4 : g));
-    ex = lookback<BLOCK, E>(a.flags + base, a.ctr + 2, tag, t, G, op, load_agg, expand, s_part,
-                            s_lp);
+    ex = lookback<BLOCK, E>(a.flags + base, a.ctr + 2, tag, t, G, op, load_agg, expand,
+                            try_expand, s_part, s_lp);
   }
   if (wid == 0 && t > 0) {
     St<N, R> st;

@@ -173,21 +173,52 @@ template <class R, class E> KF_DEV void tag_load(E& x, const u64* __restrict__ p
 //   load_agg(idx, E&)    : element published with LB_AGG by tile idx
 //   expand(idx, E&)      : element form of tile idx's anchored prefix
 //   s_part, s_lp         : LDS scratch, BLOCK/64 entries each
-template <int BLOCK, class E, class Op, class LoadAgg, class Expand>
+template <int BLOCK, class E, class Op, class LoadAgg, class Expand, class TryExpand>
 KF_DEV E lookback(const int* __restrict__ flags, unsigned* err, unsigned tag, long t, int G, Op op,
-                  LoadAgg load_agg, Expand expand, E* s_part, int* s_lp) {
+                  LoadAgg load_agg, Expand expand, TryExpand try_expand, E* s_part, int* s_lp) {
   constexpr int NW = BLOCK / WAVE;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
-  // fast path: the nearest predecessor has published its anchored prefix
-  if (tid == 0) s_lp[0] = lb_wait_flag(flags + (t - 1), tag, err);
+  // Fast path: the nearest predecessor publishes its anchored prefix.  Every
+  // payload word carries the pass tag, so a payload read whole with the tag
+  // is that prefix: one thread polls the payload and the status word
+  // together (one round of memory latency per poll) and hands the prefix to
+  // the workgroup through LDS; a status of LB_AGG without the prefix sends
+  // the workgroup to the windowed look-back.
+  if (tid == 0) {
+    const unsigned want = tag & 0x3fffffffu;
+    unsigned spins = 0;
+    int st = LB_EMPTY;
+    while (true) {
+      E v;
+      if (try_expand(t - 1, v)) {
+        s_part[0] = v;
+        st = LB_PREFIX;
+        break;
+      }
+      const unsigned fv = (unsigned)__hip_atomic_load(flags + (t - 1), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+      if ((fv >> 2) == want && (fv & 3u) == (unsigned)LB_AGG) {
+        st = LB_AGG;
+        break;
+      }
+      if (++spins >= LB_SPIN_LIMIT) {  // give up: the result is flagged invalid
+        atomicOr(err, 1u);
+        s_part[0] = v;
+        st = LB_PREFIX;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_lp[0] = st;
+  }
   __syncthreads();
   const int f1 = s_lp[0];
-  __syncthreads();
   if (f1 == LB_PREFIX) {
-    E v;
-    expand(t - 1, v);
+    const E v = s_part[0];
+    __syncthreads();  // s_part is scratch of the caller's later steps
     return v;
   }
+  __syncthreads();
   E acc;
   bool have = false;
   long j = t - 1;
