@@ -849,9 +849,13 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   __shared__ unsigned s_tag;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   if (tid == 0) {
+    // The epoch word changes only when this pass's last workgroup finishes,
+    // after every workgroup has started, so it is read before the ticket and
+    // both are in flight together.
+    const unsigned epoch = ld_relaxed(a.ctr + 3);
     const long g = (long)atomicAdd(a.ctr, 1u);
     s_tile = g;
-    s_tag = ld_relaxed(a.ctr + 3) + 1u;
+    s_tag = epoch + 1u;
     SeqInfo si;
     long sq, tt, bs;
     if (a.tile_seq) {

@@ -822,9 +822,12 @@ KF_DEV void gscan_tile(Pipe& pp, const ScanArgs<R>& a) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
   const int grp = tid / G, r = tid % G, gw = lane / G;
   if (tid == 0) {
+    // read before the ticket, as in scan_tile: the epoch word changes only
+    // when this pass's last workgroup finishes
+    const unsigned epoch = ld_relaxed(a.ctr + 3);
     const long g = (long)atomicAdd(a.ctr, 1u);
     s_tile = g;
-    s_tag = ld_relaxed(a.ctr + 3) + 1u;
+    s_tag = epoch + 1u;
     SeqInfo si;
     long sq, tt, bs;
     if (a.tile_seq) {
