@@ -170,6 +170,7 @@ kf_status run_shape(Op op, int stages, const Job& p, char* ws, const Layout& L,
     a.agg = reinterpret_cast<u64*>(ws + L.agg[slot]);
     a.pre = reinterpret_cast<u64*>(ws + L.pre[slot]);
     a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
+    a.epoch = reinterpret_cast<unsigned*>(ws + L.epoch[slot]);
     a.T = p.T;
     a.ntiles = L.ntiles[slot];
     a.nseq = p.nseq;
@@ -264,6 +265,7 @@ kf_status run_wide(Op op, int stages, const Job& p, char* ws, const Layout& L, h
     a.agg = reinterpret_cast<u64*>(ws + L.agg[slot]);
     a.pre = reinterpret_cast<u64*>(ws + L.pre[slot]);
     a.ctr = reinterpret_cast<unsigned*>(ws + L.ctr[slot]);
+    a.epoch = reinterpret_cast<unsigned*>(ws + L.epoch[slot]);
     a.T = p.T;
     a.ntiles = L.ntiles[slot];
     a.nseq = p.nseq;

@@ -446,7 +446,8 @@ template <class R> struct ScanArgs {
   int* flags;      // [nseq * ntiles] status words
   u64* agg;        // [nseq * ntiles][elem size * kWords]
   u64* pre;        // [nseq * ntiles][anchored prefix size * kWords]
-  unsigned* ctr;   // [0] tile ticket, [1] finished blocks, [2] look-back timeout flag, [3] epoch
+  unsigned* ctr;   // [0] tile ticket, [1] finished blocks, [2] look-back timeout flag
+  unsigned* epoch; // the epoch of the previous pass (its tag), on a cache line of its own
   long T;
   long ntiles;     // tiles per sequence
   long nseq;
@@ -732,13 +733,13 @@ KF_DEV SElem<N, typename P::R> rts_element_tv(const TvModel<typename P::R>& tv, 
 // another preparation launch (its successor's tag differs from every tag this
 // pass wrote).  Every block took its ticket and read the epoch before any
 // block can be last.  The timeout flag (ctr[2]) is left for diagnosis.
-KF_DEV void finish_grid(unsigned* __restrict__ ctr, unsigned tag) {
+KF_DEV void finish_grid(unsigned* __restrict__ ctr, unsigned* __restrict__ epoch, unsigned tag) {
   if (threadIdx.x == 0) {
     const unsigned done = atomicAdd(ctr + 1, 1u);
     if (done == gridDim.x - 1) {
       st_relaxed(ctr + 0, 0u);
       st_relaxed(ctr + 1, 0u);
-      st_relaxed(ctr + 3, tag);
+      st_relaxed(epoch, tag);
     }
   }
 }
@@ -852,7 +853,7 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
     // The epoch word changes only when this pass's last workgroup finishes,
     // after every workgroup has started, so it is read before the ticket and
     // both are in flight together.
-    const unsigned epoch = ld_relaxed(a.ctr + 3);
+    const unsigned epoch = ld_relaxed(a.epoch);
     const long g = (long)atomicAdd(a.ctr, 1u);
     s_tile = g;
     s_tag = epoch + 1u;
@@ -886,7 +887,7 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   const long gt = s_tile;
   const unsigned tag = s_tag;
   if (s_seq < 0) {  // a ragged batch's grid has spare blocks past the last tile
-    finish_grid(a.ctr, tag);
+    finish_grid(a.ctr, a.epoch, tag);
     return;
   }
   // values read from LDS are the same in every lane; say so, so that the
@@ -1019,7 +1020,7 @@ KF_DEV void scan_tile(Pipe& pp, const ScanArgs<R>& a) {
   } else {
     pp.steps(st, have);
   }
-  finish_grid(a.ctr, tag);
+  finish_grid(a.ctr, a.epoch, tag);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,7 @@
 namespace kfs {
 
 constexpr int kBlock = 256;
+constexpr size_t kEpochOffset = 128;  // bytes: the epoch words of the two scan slots
 
 // Time steps each thread owns (L), at most: in the scans over full elements,
 // and in the time-invariant filter, whose per-thread fold is a linear map of
@@ -65,7 +66,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // zeroed by the preparation kernel at the start of every call, so a workspace
 // needs no initialisation and carries no state from one call to the next.
 struct Layout {
-  size_t ctr[2];              // [0] tile ticket, [1] finished blocks, [2] timeout flag, [3] epoch
+  size_t ctr[2];              // [0] tile ticket, [1] finished blocks, [2] timeout flag
+  size_t epoch[2];            // the pass epoch of each slot, a cache line away from the tickets
   size_t flags[2];            // look-back status words, slot 0 forward, slot 1 backward
   size_t agg[2];              // published tile aggregates (tagged 64-bit words)
   size_t pre[2];              // published anchored prefixes (tagged 64-bit words)
@@ -234,6 +236,10 @@ inline Layout make_layout(const Job& j) {
     L.ctr[s] = off;
     off += 4 * sizeof(unsigned);
   }
+  // Every workgroup reads its slot's epoch as it takes its ticket; on the
+  // tickets' cache line those reads would queue behind the ticket atomics.
+  for (int s = 0; s < 2; ++s) L.epoch[s] = kEpochOffset + 64 * (size_t)s;
+  off = kEpochOffset + 128;
   for (int s = 0; s < 2; ++s) {
     L.flags[s] = off;
     off += (size_t)L.grid[s] * sizeof(int);

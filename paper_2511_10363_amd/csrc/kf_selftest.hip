@@ -309,7 +309,7 @@ static SelftestLayout selftest_layout(int precision, int group, int items, long 
   // driver; one row per lane of a group in the group driver
   const size_t ew = group == 1 ? 10 : (size_t)group * 10;
   const size_t pw = group == 1 ? 6 : (size_t)group * (group + 1);
-  size_t off = 8 * sizeof(unsigned);
+  size_t off = kEpochOffset + 128;  // the counters of two slots, then their epochs
   L.flags = off;
   off += (size_t)grid * sizeof(int);
   off = (off + 7) & ~size_t(7);
@@ -347,6 +347,7 @@ static kf_status selftest_run(int group, int reverse, int items, long T, long ns
   a.agg = reinterpret_cast<u64*>(ws + L.agg);
   a.pre = reinterpret_cast<u64*>(ws + L.pre);
   a.ctr = reinterpret_cast<unsigned*>(ws);
+  a.epoch = reinterpret_cast<unsigned*>(ws + kEpochOffset);
   a.T = T;
   a.ntiles = L.ntiles;
   a.nseq = nseq;

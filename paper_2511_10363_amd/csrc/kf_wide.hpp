@@ -824,7 +824,7 @@ KF_DEV void gscan_tile(Pipe& pp, const ScanArgs<R>& a) {
   if (tid == 0) {
     // read before the ticket, as in scan_tile: the epoch word changes only
     // when this pass's last workgroup finishes
-    const unsigned epoch = ld_relaxed(a.ctr + 3);
+    const unsigned epoch = ld_relaxed(a.epoch);
     const long g = (long)atomicAdd(a.ctr, 1u);
     s_tile = g;
     s_tag = epoch + 1u;
@@ -857,7 +857,7 @@ KF_DEV void gscan_tile(Pipe& pp, const ScanArgs<R>& a) {
   __syncthreads();
   const unsigned tag = s_tag;
   if (s_seq < 0) {
-    finish_grid(a.ctr, tag);
+    finish_grid(a.ctr, a.epoch, tag);
     return;
   }
   const long t = uniform(s_t);
@@ -935,7 +935,7 @@ KF_DEV void gscan_tile(Pipe& pp, const ScanArgs<R>& a) {
   for (int w = 0; w < wid; ++w) pp.apply(st, s_wt[w][r]);
   if (gw > 0) pp.apply(st, s_x[tid - G]);
   pp.steps(st);
-  finish_grid(a.ctr, tag);
+  finish_grid(a.ctr, a.epoch, tag);
 }
 
 // ---------------------------------------------------------------------------
