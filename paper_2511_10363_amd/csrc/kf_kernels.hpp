@@ -1209,6 +1209,12 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
   R* __restrict__ Po;
   R yv[L][M];
   KF_DEV FilterTiPipe(const ScanArgs<R>& a_, const IO<R>& io_) : a(a_), io(io_) {}
+  // Vector loads complete in order, so the first table entry S_L, which
+  // the table build waits for, is requested before the measurements, which
+  // are not needed until the fold.  The measurement loads are unconditional
+  // (a padded step reads the sequence's last row, and its value is then
+  // replaced by zero): a load under a per-step branch would have to complete
+  // before the branches merge, one round trip after another.
   KF_DEV void bind(const SeqInfo& s, long t, int tid) {
     T = s.T;
     k0 = t * (long)(L * blockDim.x) + (long)tid * L;
@@ -1216,10 +1222,28 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
     const R* __restrict__ y = io.y + s.row0 * M;
     mo = io.m_out + s.row0 * N;
     Po = io.P_out + s.row0 * N * N;
+    S sl[3] = {S(0), S(0), S(0)};
+    if (tid < N * N)
 #pragma unroll
-    for (int i = 0; i < L; ++i)
+      for (int q = 0; q < 3; ++q) sl[q] = S(cst[LY::SL + q * N * N + tid]);
+    // a workgroup has a tile only in a sequence with T >= 1
 #pragma unroll
-      for (int c = 0; c < M; ++c) yv[i][c] = (k0 + i < T) ? y[(k0 + i) * M + c] : R(0);
+    for (int i = 0; i < L; ++i) {
+      const bool in = k0 + i < T;
+      const long k = in ? k0 + i : T - 1;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const R v = y[k * M + c];
+        yv[i][c] = in ? v : R(0);
+      }
+    }
+    if (tid < N * N) {
+      Tables& tb = tables();
+      const int r = tid / N, j = tid % N;
+      tb.agg[0].m.A[r][j] = sl[0];
+      tb.agg[0].m.C[r][j] = sl[1];
+      tb.agg[0].m.J[r][j] = sl[2];
+    }
   }
   KF_DEV E op(const E& p, const E& q) const { return fcombine<N, P>(p, q); }
   // S_{cL} as an element with vector part v = (b, eta)
@@ -1240,13 +1264,7 @@ template <int N, int M, class P, int L, int BLOCK> struct FilterTiPipe {
   }
   KF_DEV E scan_wave(int tid, int lane) const {
     Tables& tb = tables();
-    // S_L from the model constants
-    if (tid < N * N) {
-      const int r = tid / N, j = tid % N;
-      tb.agg[0].m.A[r][j] = S(cst[LY::SL + r * N + j]);
-      tb.agg[0].m.C[r][j] = S(cst[LY::SL + N * N + r * N + j]);
-      tb.agg[0].m.J[r][j] = S(cst[LY::SL + 2 * N * N + r * N + j]);
-    }
+    // S_L, written by bind
     __syncthreads();
     // level d: S_{(a + h)L} = S_{aL} (x) S_{hL} and its coefficients, h = 2^d,
     // a = 1..h; the inputs come from earlier levels
@@ -1624,24 +1642,40 @@ template <int N, int M, class P, int L, int B, bool TV = false> struct RtsPipe {
     ms = s_mean + threadIdx.x;
     constexpr int CH = chunk<N>();
     constexpr int PER = N / CH;
+    constexpr int NJ = L * PER;
     const int lane = threadIdx.x & (WAVE - 1);
     const long base = lane_k0(WAVE - 1);
     R* col0 = ms - lane;
+    // Every load is issued before the first LDS write: a value stored as
+    // soon as it is loaded would be waited for before the next load went
+    // out.  Chunk j of lane `lane` is chunk c = j * WAVE + lane of the
+    // wavefront's rows base .. base + WAVE * L - 1, at offset c * CH from
+    // row base.  Rows past T are read from row T - 1 (a sequence has at
+    // least one step) and replaced by zeros.
+    R v[NJ][CH];
+    if (uniform(base + (long)WAVE * L - 1) < T) {
+      const R* p = mf + base * N + lane * CH;
 #pragma unroll
-    for (int j = 0; j < L * PER; ++j) {
+      for (int j = 0; j < NJ; ++j) __builtin_memcpy(v[j], p + j * WAVE * CH, sizeof(v[j]));
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int c = j * WAVE + lane;
+        const int e = (c % PER) * CH;
+        const long k = base + c / PER;
+        const bool in = k < T;
+        __builtin_memcpy(v[j], mf + (in ? k : T - 1) * N + e, sizeof(v[j]));
+#pragma unroll
+        for (int t = 0; t < CH; ++t) v[j][t] = in ? v[j][t] : R(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
       const int c = j * WAVE + lane;
       const int rr = c / PER, e = (c % PER) * CH;
-      const long k = base + rr;
       const int l = WAVE - 1 - rr / L, i = rr % L;
-      R v[CH];
-      if (k < T) {
-        __builtin_memcpy(v, mf + k * N + e, sizeof(v));
-      } else {
 #pragma unroll
-        for (int t = 0; t < CH; ++t) v[t] = R(0);
-      }
-#pragma unroll
-      for (int t = 0; t < CH; ++t) col0[(i * N + e + t) * B + l] = v[t];
+      for (int t = 0; t < CH; ++t) col0[(i * N + e + t) * B + l] = v[j][t];
     }
     wave_lds_sync();
   }
