@@ -104,13 +104,24 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
   __shared__ D mF[2][N][N], mQ[2][N][N], mH[2][M][N], mR[2][M][M];
   const int l = lane;
   const int wv = tid / WAVE;
+  // The model is read with every load issued before the first LDS write, so
+  // that the reads take one round trip instead of one per matrix: lanes past
+  // a matrix's size read its entry 0 and do not store it.  Wavefront 1 also
+  // reads m0 and P0 here.
+  D ld_p0 = D(0), ld_m0 = D(0);
   if (wv < 2) {
-    if (l < N * N) {
-      mF[wv][l / N][l % N] = D(F_[l]);
-      mQ[wv][l / N][l % N] = D(Q_[l]);
+    const int lf = l < N * N ? l : 0, lh = l < M * N ? l : 0, lr = l < M * M ? l : 0;
+    const D f = D(F_[lf]), q = D(Q_[lf]), h = D(H_[lh]), r = D(R_[lr]);
+    if (wv == 1) {
+      ld_p0 = D(P0_[lf]);
+      ld_m0 = D(m0_[l < N ? l : 0]);
     }
-    if (l < M * N) mH[wv][l / N][l % N] = D(H_[l]);
-    if (l < M * M) mR[wv][l / M][l % M] = D(R_[l]);
+    if (l < N * N) {
+      mF[wv][l / N][l % N] = f;
+      mQ[wv][l / N][l % N] = q;
+    }
+    if (l < M * N) mH[wv][l / N][l % N] = h;
+    if (l < M * M) mR[wv][l / M][l % M] = r;
     wave_lds_sync();
   }
   if (wv == 0) {
@@ -202,8 +213,8 @@ __global__ __launch_bounds__(256) void k_prepare(const R* __restrict__ F_, const
     const D(&Rm)[M][M] = mR[1];
     __shared__ D fP0[N][N], fm0[N], fx[N], fFP[N][N], fP[N][N], fHP[M][N], fHx[M], fS[M][M],
         fK[M][N];
-    if (l < N * N) fP0[l / N][l % N] = D(P0_[l]);
-    if (l < N) fm0[l] = D(m0_[l]);
+    if (l < N * N) fP0[l / N][l % N] = ld_p0;
+    if (l < N) fm0[l] = ld_m0;
     wave_lds_sync();
     if (l < N * N) {  // copies: F, Q and P0 symmetrised, m0
       const int i = l / N, j = l % N;
