@@ -43,18 +43,24 @@ FP64_VALU_PEAK = 78.6e12       # MI355X vector FP64 FLOP/s
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources and of the compile flags (less the include
+    path, which depends on where the repository sits)."""
+    from paper_2511_10363_amd import build as kbuild
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_10363_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hpp", ".hip")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
+    inc = os.path.join(kbuild.ROOT, "include")
+    h.update(" ".join(f for f in kbuild.CXXFLAGS if f != inc).encode())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str, workload: str, precision: str):
     """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json),
-    only if the kernel sources have not changed since the counters were taken."""
+    only if the kernel sources and compile flags have not changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
